@@ -1,0 +1,191 @@
+/*
+ * floquet.h -- C ABI of the MI355X (gfx950) polynomial-filter Floquet
+ * eigensolver.
+ *
+ * The library finds the eigenpairs of a many-qubit Floquet unitary U (one
+ * driving period, dimension d = 2^L) whose eigenvalues lie closest to a target
+ * e^{i phi} on the unit circle, by running Arnoldi on the geometric-sum filter
+ *     g_k(U) = sum_{n=0..k} (e^{-i phi} U)^n            (Sec. 3, Eq. (geo))
+ * and recovering omega_n = <n|U|n> with residual ||U|n> - omega_n|n>||
+ * (Sec. 4, Eq. (residual)).  U is never stored: it is applied matrix-free.
+ *
+ * Conventions shared by every entry point
+ *  - A state is d = 2^L amplitudes in natural index order, interleaved
+ *    complex: complex64 = {float re, im}, complex128 = {double re, im}.
+ *  - Site i (1-based) of the chain is bit L-i of the index (site 1 = most
+ *    significant bit; the C-order reshaping of Eq. (matvec) and Eq. (ee)).
+ *  - Pointers named *_dev are device (HBM) pointers owned by the caller, e.g.
+ *    torch tensors' data_ptr(); *_host pointers are host memory owned by the
+ *    caller.  The library never frees caller memory.
+ *  - hip_stream is a hipStream_t (NULL = the null stream).  apply_U and
+ *    apply_filter are asynchronous on that stream; arnoldi_eigs* are
+ *    host-driven and return after all their device work has finished.
+ *  - No entry point throws.  Every call returns an fq_status; on failure
+ *    floquet_last_error() gives a message for the calling thread.
+ *  - An op is not thread-safe: one host thread (and one stream) at a time.
+ */
+#ifndef FLOQUET_H
+#define FLOQUET_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct floquet_op floquet_op; /* opaque; owned by the library */
+
+typedef enum {
+  FQ_OK = 0,
+  FQ_NOT_CONVERGED = 1, /* partial results are valid, see stats.nconv */
+  FQ_EINVAL = -1,       /* bad argument (size, pointer, option) */
+  FQ_ENOMEM = -2,       /* device or host allocation failed */
+  FQ_EDEVICE = -3,      /* a HIP call failed (no device, launch error, ...) */
+  FQ_ENUMERIC = -4      /* NaN/Inf, or a Krylov breakdown without an invariant subspace */
+} fq_status;
+
+typedef enum { FQ_C64 = 0, FQ_C128 = 1 } fq_dtype;
+
+typedef enum { FQ_KICKED_ISING = 0, FQ_BRICKWORK = 1 } fq_model;
+
+/*
+ * Model description (host memory, copied by create_floquet_op).
+ *
+ * FQ_KICKED_ISING: U = D K with K = prod_i exp(-i g X_i) acting first and
+ *   D = diag exp(-i E(s)), E(s) = sum_i J_i z_i z_{i+1} + h_i z_i, z_i = 1-2b_i.
+ *   J[L], h[L]: J[i-1] couples sites i, i+1; with periodic != 0 the bond
+ *   (L, 1) uses J[L-1], otherwise J[L-1] is ignored.  gates must be NULL.
+ *
+ * FQ_BRICKWORK: the two-layer brickwork circuit of Sec. 2, Eq. (U) and
+ *   Eq. (unitary): U = U_a U_b, U_b acting first.  gates is a flat complex128
+ *   array (interleaved re, im) of n_gates = L + 1 matrices: first U_b's gates,
+ *   then U_a's, each layer from site 1 to site L.  For even L,
+ *     U_b = u_1, u_{2,3}, u_{4,5}, ..., u_{L-2,L-1}, u_L   and
+ *     U_a = u_{1,2}, u_{3,4}, ..., u_{L-1,L};
+ *   for odd L, U_b = u_1, u_{2,3}, ..., u_{L-1,L} and
+ *     U_a = u_{1,2}, ..., u_{L-2,L-1}, u_L.
+ *   Two-site gates are row-major 4x4 with local index 2 b_i + b_{i+1};
+ *   one-site gates are row-major 2x2.  J, h must be NULL.
+ *
+ * L must satisfy 2 <= L <= 30.
+ */
+typedef struct {
+  fq_model model;
+  int L;
+  int periodic;
+  const double* J;
+  const double* h;
+  double g;
+  const double* gates;
+  int n_gates;
+} fq_model_desc;
+
+/* Build an operator: copies the model, builds device phase/gate tables.
+ * Returns FQ_EINVAL for a bad description, FQ_EDEVICE without a usable GPU. */
+fq_status create_floquet_op(const fq_model_desc* desc, floquet_op** out);
+
+/* Frees the op, its tables and its Krylov workspace.  NULL is accepted. */
+fq_status destroy_floquet_op(floquet_op* op);
+
+/* d = 2^L of the op (0 for NULL). */
+long long floquet_op_dim(const floquet_op* op);
+
+/*
+ * out = U psi (Sec. 2; the product the filter is built from).
+ * psi_dev, out_dev: d amplitudes of dtype.  In-place (out == psi) is allowed.
+ * Asynchronous on hip_stream.
+ */
+fq_status apply_U(floquet_op* op, fq_dtype dtype, const void* psi_dev, void* out_dev,
+                  void* hip_stream);
+
+/*
+ * out = g_k(U) psi = sum_{n=0..k} (e^{-i phi} U)^n psi   (Sec. 3, Eq. (geo)),
+ * evaluated by the Horner recurrence w <- psi + e^{-i phi} U w, k times from
+ * w = psi.  k >= 0; k = 0 copies psi.  out must not alias psi.
+ * Asynchronous on hip_stream.
+ */
+fq_status apply_filter(floquet_op* op, int k, double phi, fq_dtype dtype,
+                       const void* psi_dev, void* out_dev, void* hip_stream);
+
+/*
+ * out = sum_{m=0..k} a_m U^m psi, a general polynomial filter (Sec. 3,
+ * Eq. (poly)), evaluated by Horner's rule w <- a_{m} psi + U w from w = a_k psi.
+ * coeffs_host: k+1 complex128 coefficients a_0..a_k (interleaved re, im).
+ * out must not alias psi.  Asynchronous on hip_stream.
+ */
+fq_status apply_polynomial(floquet_op* op, int k, const double* coeffs_host, fq_dtype dtype,
+                           const void* psi_dev, void* out_dev, void* hip_stream);
+
+/* Options of arnoldi_eigs. */
+typedef struct {
+  int k;                   /* filter order (>= 0) */
+  int ncv;                 /* Krylov dimension, nev + 2 <= ncv <= min(d, 3000) */
+  double tol;              /* residual tolerance on ||U v - omega v|| */
+  int max_restarts;        /* Krylov-Schur restarts before FQ_NOT_CONVERGED */
+  fq_dtype filter_dtype;   /* FQ_C64: filter in complex64, rest FP64 */
+  int refine;              /* with FQ_C64: finish in FP64 until tol is met */
+  unsigned long long seed; /* start vector seed when v0_dev is NULL */
+  const void* v0_dev;      /* optional complex128 start vector (d), or NULL */
+} fq_arnoldi_opts;
+
+/* Counters and per-phase wall times (seconds) of one solve. */
+typedef struct {
+  int nconv;                 /* eigenpairs meeting tol */
+  int n_restarts;            /* Krylov-Schur restarts, both phases */
+  long long n_filter_apps;   /* g_k(U) applications */
+  long long n_U_apps;        /* U applications, filter and residual checks */
+  long long n_U_apps_c64;    /* of which in complex64 */
+  double t_filter, t_orth, t_restart, t_refine, t_total;
+  double max_residual;       /* max over the returned pairs */
+} fq_arnoldi_stats;
+
+/*
+ * The nev eigenpairs of U closest to e^{i phi} (Sec. 3-4): Krylov-Schur
+ * Arnoldi on g_k(U) selecting the largest |lambda| (Sec. 4, Eq. (arnoldi)),
+ * then omega_n = <n|U|n> and r_n = ||U|n> - omega_n|n>|| in FP64.
+ *
+ * evals_host:  2*nev doubles, omega_n interleaved (re, im), sorted by
+ *              |arg(omega e^{-i phi})| ascending (Rayleigh quotients, not
+ *              renormalised onto the circle).
+ * evecs_dev:   d x nev complex128, column-major (vector n at offset n*d),
+ *              unit 2-norm, arbitrary phase.  May be NULL.
+ * resid_host:  nev doubles r_n.  May be NULL.
+ * stats:       may be NULL.
+ * The op keeps a d x ncv complex128 workspace between calls (freed by
+ * destroy_floquet_op).  Returns FQ_NOT_CONVERGED (results valid for the
+ * first stats.nconv pairs) when max_restarts is reached, FQ_ENOMEM when the
+ * workspace does not fit, FQ_EINVAL for nev < 1, ncv < nev + 2, ncv > min(d, 3000),
+ * k < 0 or tol <= 0.
+ */
+fq_status arnoldi_eigs(floquet_op* op, int nev, double phi, const fq_arnoldi_opts* opts,
+                       double* evals_host, void* evecs_dev, double* resid_host,
+                       fq_arnoldi_stats* stats, void* hip_stream);
+
+/*
+ * Many independent problems in one call: every op in ops[0..n_ops) and every
+ * target in phis[0..n_phi) (problem p = i*n_phi + j).  Ops may have different L.
+ * evals_host: n_ops*n_phi*2*nev doubles; evecs_dev: n_ops*n_phi pointers (each
+ * d_i x nev complex128, or NULL); resid_host: n_ops*n_phi*nev doubles or NULL;
+ * stats: n_ops*n_phi entries or NULL.  Returns the worst status over problems.
+ */
+fq_status arnoldi_eigs_batched(floquet_op* const* ops, int n_ops, const double* phis, int n_phi,
+                               int nev, const fq_arnoldi_opts* opts, double* evals_host,
+                               void* const* evecs_dev, double* resid_host,
+                               fq_arnoldi_stats* stats, void* hip_stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* floquet_last_error(void);
+
+/*
+ * Host-only helper exposed for testing the small dense step of the restart:
+ * complex Schur form A = Z T Z^H of an n x n complex128 matrix (column-major,
+ * interleaved), reordered so that the eigenvalues of largest modulus come
+ * first.  a_host is overwritten by T; z_host receives Z (n x n); w_host
+ * receives the n eigenvalues (diagonal of T).  Returns FQ_ENUMERIC if the QR
+ * iteration does not converge.
+ */
+fq_status fq_host_schur(int n, double* a_host, double* z_host, double* w_host);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLOQUET_H */

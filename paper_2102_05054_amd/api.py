@@ -1,0 +1,204 @@
+"""Python face of the C ABI: the same entry points, taking torch tensors.
+
+PyTorch only supplies device memory (``data_ptr()``) and the current HIP
+stream; every computation happens in libfloquet.so.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from ctypes import POINTER, c_double, c_void_p
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib
+from ._lib import (FQ_BRICKWORK, FQ_C64, FQ_C128, FQ_KICKED_ISING, FQ_NOT_CONVERGED, FQ_OK,
+                   FqArnoldiOpts, FqArnoldiStats, FqModelDesc, check, lib)
+
+__all__ = ["FloquetOp", "kicked_ising", "brickwork", "arnoldi_eigs_batched", "host_schur"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.complex64:
+        return FQ_C64
+    if t.dtype == torch.complex128:
+        return FQ_C128
+    raise TypeError(f"state tensors must be complex64 or complex128, got {t.dtype}")
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    return c_void_p(t.data_ptr())
+
+
+def _dbl_array(x):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    return a, a.ctypes.data_as(POINTER(c_double))
+
+
+class FloquetOp:
+    """Owns one ``floquet_op`` handle (create_floquet_op / destroy_floquet_op)."""
+
+    def __init__(self, desc: FqModelDesc, keep=()):
+        self._keep = keep
+        h = c_void_p()
+        check(lib().create_floquet_op(ctypes.byref(desc), ctypes.byref(h)), "create_floquet_op")
+        self.handle = h
+        self.L = desc.L
+        self.dim = int(lib().floquet_op_dim(h))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            check(lib().destroy_floquet_op(self.handle), "destroy_floquet_op")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- checks ----------------------------------------------------------
+    def _check_state(self, t, name):
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be a device tensor")
+        if not t.is_contiguous() or t.numel() != self.dim:
+            raise ValueError(f"{name} must be contiguous with {self.dim} elements")
+
+    # -- entry points ----------------------------------------------------
+    def apply_U(self, psi, out=None, stream=None):
+        """out = U psi."""
+        torch = _torch()
+        self._check_state(psi, "psi")
+        out = torch.empty_like(psi) if out is None else out
+        self._check_state(out, "out")
+        if out.dtype != psi.dtype:
+            raise TypeError("psi and out must have the same dtype")
+        check(lib().apply_U(self.handle, _dtype_code(psi), _dptr(psi), _dptr(out), _stream_ptr(stream)), "apply_U")
+        return out
+
+    def apply_filter(self, psi, k: int, phi: float, out=None, stream=None):
+        """out = sum_{n=0..k} (e^{-i phi} U)^n psi."""
+        torch = _torch()
+        self._check_state(psi, "psi")
+        out = torch.empty_like(psi) if out is None else out
+        self._check_state(out, "out")
+        if out.dtype != psi.dtype:
+            raise TypeError("psi and out must have the same dtype")
+        check(lib().apply_filter(self.handle, int(k), float(phi), _dtype_code(psi), _dptr(psi), _dptr(out),
+                                 _stream_ptr(stream)), "apply_filter")
+        return out
+
+    def apply_polynomial(self, psi, coeffs: Sequence[complex], out=None, stream=None):
+        """out = sum_m coeffs[m] U^m psi."""
+        torch = _torch()
+        self._check_state(psi, "psi")
+        out = torch.empty_like(psi) if out is None else out
+        self._check_state(out, "out")
+        c = np.asarray(coeffs, dtype=np.complex128)
+        flat, ptr = _dbl_array(np.stack([c.real, c.imag], axis=1).reshape(-1))
+        check(lib().apply_polynomial(self.handle, len(c) - 1, ptr, _dtype_code(psi), _dptr(psi), _dptr(out),
+                                     _stream_ptr(stream)), "apply_polynomial")
+        return out
+
+    def arnoldi_eigs(self, nev: int, phi: float, *, k: int, ncv: int, tol: float = 1e-10,
+                     max_restarts: int = 200, filter_dtype: str = "c128", refine: bool = True,
+                     seed: int = 0, v0=None, want_vectors: bool = True, stream=None,
+                     allow_not_converged: bool = False):
+        """Eigenpairs of U closest to e^{i phi}.  Returns (evals, evecs, resid, stats, status)."""
+        torch = _torch()
+        opts = FqArnoldiOpts(k=int(k), ncv=int(ncv), tol=float(tol), max_restarts=int(max_restarts),
+                             filter_dtype=FQ_C64 if filter_dtype == "c64" else FQ_C128,
+                             refine=1 if refine else 0, seed=int(seed),
+                             v0_dev=c_void_p(v0.data_ptr()) if v0 is not None else None)
+        if v0 is not None:
+            self._check_state(v0, "v0")
+            if v0.dtype != torch.complex128:
+                raise TypeError("v0 must be complex128")
+        evals = np.zeros(2 * nev)
+        resid = np.zeros(nev)
+        stats = FqArnoldiStats()
+        evecs = None
+        if want_vectors:
+            evecs = torch.empty((nev, self.dim), dtype=torch.complex128, device="cuda")
+        st = lib().arnoldi_eigs(self.handle, int(nev), float(phi), ctypes.byref(opts),
+                                evals.ctypes.data_as(POINTER(c_double)),
+                                _dptr(evecs) if evecs is not None else None,
+                                resid.ctypes.data_as(POINTER(c_double)), ctypes.byref(stats),
+                                _stream_ptr(stream))
+        check(st, "arnoldi_eigs", allow=(FQ_OK, FQ_NOT_CONVERGED) if allow_not_converged else (FQ_OK,))
+        return evals[0::2] + 1j * evals[1::2], evecs, resid, stats.as_dict(), st
+
+
+def kicked_ising(L: int, J, h, g: float, periodic: bool = True) -> FloquetOp:
+    """Kicked-Ising U = D K (see include/floquet.h)."""
+    Ja, Jp = _dbl_array(J)
+    ha, hp = _dbl_array(h)
+    if Ja.size != L or ha.size != L:
+        raise ValueError("J and h need L entries")
+    desc = FqModelDesc(model=FQ_KICKED_ISING, L=int(L), periodic=1 if periodic else 0, J=Jp, h=hp,
+                       g=float(g), gates=None, n_gates=0)
+    return FloquetOp(desc, keep=(Ja, ha))
+
+
+def brickwork(L: int, gates) -> FloquetOp:
+    """Brickwork U = U_a U_b from the flat complex128 gate array."""
+    g = np.ascontiguousarray(np.asarray(gates, dtype=np.complex128))
+    flat, ptr = _dbl_array(np.stack([g.real, g.imag], axis=1).reshape(-1))
+    desc = FqModelDesc(model=FQ_BRICKWORK, L=int(L), periodic=0, J=None, h=None, g=0.0, gates=ptr,
+                       n_gates=int(L) + 1)
+    return FloquetOp(desc, keep=(flat,))
+
+
+def arnoldi_eigs_batched(ops: Sequence[FloquetOp], phis: Sequence[float], nev: int, *, k: int, ncv: int,
+                         tol: float = 1e-10, max_restarts: int = 200, filter_dtype: str = "c128",
+                         refine: bool = True, seed: int = 0, stream=None, allow_not_converged=False):
+    """All (op, phi) problems in one call.  Returns (evals[n_ops, n_phi, nev], resid, stats, status)."""
+    n_ops, n_phi = len(ops), len(phis)
+    handles = (c_void_p * n_ops)(*[o.handle for o in ops])
+    ph, php = _dbl_array(phis)
+    opts = FqArnoldiOpts(k=int(k), ncv=int(ncv), tol=float(tol), max_restarts=int(max_restarts),
+                         filter_dtype=FQ_C64 if filter_dtype == "c64" else FQ_C128,
+                         refine=1 if refine else 0, seed=int(seed), v0_dev=None)
+    evals = np.zeros(n_ops * n_phi * 2 * nev)
+    resid = np.zeros(n_ops * n_phi * nev)
+    stats = (FqArnoldiStats * (n_ops * n_phi))()
+    st = lib().arnoldi_eigs_batched(handles, n_ops, php, n_phi, int(nev), ctypes.byref(opts),
+                                    evals.ctypes.data_as(POINTER(c_double)), None,
+                                    resid.ctypes.data_as(POINTER(c_double)), stats, _stream_ptr(stream))
+    check(st, "arnoldi_eigs_batched", allow=(FQ_OK, FQ_NOT_CONVERGED) if allow_not_converged else (FQ_OK,))
+    ev = (evals[0::2] + 1j * evals[1::2]).reshape(n_ops, n_phi, nev)
+    return ev, resid.reshape(n_ops, n_phi, nev), [s.as_dict() for s in stats], st
+
+
+def host_schur(A: np.ndarray):
+    """Host-only helper: complex Schur form with largest |eigenvalue| first.  Returns (T, Z, w)."""
+    A = np.asarray(A, dtype=np.complex128)
+    n = A.shape[0]
+    a = np.ascontiguousarray(A.T).reshape(-1)  # column-major
+    ab = np.stack([a.real, a.imag], axis=1).reshape(-1).copy()
+    zb = np.zeros(2 * n * n)
+    wb = np.zeros(2 * n)
+    check(lib().fq_host_schur(n, ab.ctypes.data_as(POINTER(c_double)), zb.ctypes.data_as(POINTER(c_double)),
+                              wb.ctypes.data_as(POINTER(c_double))), "fq_host_schur")
+    T = (ab[0::2] + 1j * ab[1::2]).reshape(n, n).T
+    Z = (zb[0::2] + 1j * zb[1::2]).reshape(n, n).T
+    return T, Z, wb[0::2] + 1j * wb[1::2]

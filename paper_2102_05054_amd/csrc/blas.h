@@ -1,0 +1,51 @@
+// FP64 vector kernels of the Krylov side (library-internal launch interface).
+//
+// Basis layout: V is d x ncols complex128, column-major with leading
+// dimension ldv (column i at V + i*ldv), one Krylov vector per column.
+#pragma once
+
+#include "common.h"
+
+namespace fq {
+
+// rows handled by one workgroup of the row-blocked kernels
+constexpr int kRowsPerThread = 4;
+constexpr int kBlockThreads = 256;
+inline unsigned row_blocks(size_t d) {
+  const size_t per = size_t(kRowsPerThread) * kBlockThreads;
+  return static_cast<unsigned>((d + per - 1) / per);
+}
+
+// partial[b*ldp + i] = sum_{rows r of block b} conj(V[r, i]) * w[r],  i < ncols
+hipError_t launch_dots(const c128* V, size_t ldv, int ncols, const c128* w, size_t d, c128* partial, int ldp,
+                       hipStream_t s);
+// out[i] = sum_b partial[b*ldp + i]; if acc != NULL also acc[i] += out[i]
+hipError_t launch_reduce_cols(const c128* partial, int ldp, unsigned nblk, int ncols, c128* out, hipStream_t s);
+// w -= V h  (h: ncols complex128 on the device)
+hipError_t launch_update(const c128* V, size_t ldv, int ncols, const c128* h, c128* w, size_t d, hipStream_t s);
+// fused: w -= V h, then partial dots of the updated w against V (one read of V per row block
+// for the update, one for the dots, issued back to back so the second read hits cache)
+hipError_t launch_update_dots(const c128* V, size_t ldv, int ncols, const c128* h, c128* w, size_t d,
+                              c128* partial, int ldp, hipStream_t s);
+// partial[b] = sum_{rows r of block b} |w[r]|^2 (stored in .x)
+hipError_t launch_norm2(const c128* w, size_t d, c128* partial, hipStream_t s);
+// w -= V h, then partial[b] = sum |w|^2 over the block's rows
+hipError_t launch_update_norm2(const c128* V, size_t ldv, int ncols, const c128* h, c128* w, size_t d,
+                               c128* partial, hipStream_t s);
+// nrm[0] = sqrt(sum_b partial[b].x), nrm[1] = 1/nrm[0] (0 if nrm[0] == 0)
+hipError_t launch_reduce_norm(const c128* partial, unsigned nblk, double* nrm, hipStream_t s);
+// out = in * scale[0] (scale read from device memory)
+hipError_t launch_scale_dev(const c128* in, const double* scale, c128* out, size_t d, hipStream_t s);
+// out = a * in
+hipError_t launch_scale_c128(const c128* in, double are, double aim, c128* out, size_t d, hipStream_t s);
+hipError_t launch_scale_c64(const c64* in, double are, double aim, c64* out, size_t d, hipStream_t s);
+// y = y - a * x   (a on the device, complex)
+hipError_t launch_axpy_dev(const c128* a, const c128* x, c128* y, size_t d, hipStream_t s);
+// Y[:, c] = sum_{i<m} V[:, i] Q[i, c] for c < p.  Y may equal V (in place, p <= m).
+// Q: m x p complex128 column-major (ldq = m) on the device.
+hipError_t launch_basis_gemm(const c128* V, size_t ldv, int m, const c128* Q, int p, c128* Y, size_t ldy,
+                             size_t d, hipStream_t s);
+// v[i] = counter-based uniform complex in [-1, 1)^2 from (seed, i)
+hipError_t launch_random(c128* v, size_t d, unsigned long long seed, hipStream_t s);
+
+}  // namespace fq

@@ -1,0 +1,403 @@
+// FP64 kernels of the Krylov side: Gram-Schmidt projections, norms, scaling,
+// the restart / Ritz-vector basis product and the start vector.
+//
+// The projections h = V^H w and w -= V h with a single new vector are
+// matrix-vector products (0.5 flop per byte of V), bound by HBM bandwidth;
+// they stream V column by column with every lane reading consecutive rows.
+// Reductions use a fixed tree (wavefront shuffles, then the four waves), so
+// results are bitwise reproducible for a given launch shape.
+#include "blas.h"
+
+namespace fq {
+
+namespace {
+
+constexpr int RPT = kRowsPerThread;
+constexpr int NT = kBlockThreads;
+constexpr int NCH = 8;  // columns per reduction round
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+  return v;
+}
+
+// Reduce NCH complex per-thread values over the block; thread c < nvalid
+// receives value c in (ox, oy).
+__device__ __forceinline__ void block_sum_nch(double (&ax)[NCH], double (&ay)[NCH], double (*red)[2 * NCH],
+                                              int tid) {
+  const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    ax[c] = wave_sum(ax[c]);
+    ay[c] = wave_sum(ay[c]);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      red[wv][2 * c] = ax[c];
+      red[wv][2 * c + 1] = ay[c];
+    }
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(NT) dots_kernel(const c128* __restrict__ V, size_t ldv, int ncols,
+                                                  const c128* __restrict__ w, size_t d, c128* __restrict__ partial,
+                                                  int ldp) {
+  __shared__ double red[NT / 64][2 * NCH];
+  const int tid = threadIdx.x;
+  const size_t r0 = static_cast<size_t>(blockIdx.x) * NT * RPT + tid;
+  c128 wr[RPT];
+  bool ok[RPT];
+#pragma unroll
+  for (int t = 0; t < RPT; ++t) {
+    const size_t r = r0 + size_t(t) * NT;
+    ok[t] = r < d;
+    wr[t] = ok[t] ? w[r] : mk<double>(0, 0);
+  }
+  for (int i0 = 0; i0 < ncols; i0 += NCH) {
+    double ax[NCH], ay[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      ax[c] = 0.0;
+      ay[c] = 0.0;
+      if (i0 + c < ncols) {
+        const c128* col = V + size_t(i0 + c) * ldv;
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) {
+          if (ok[t]) {
+            const c128 v = col[r0 + size_t(t) * NT];
+            ax[c] += v.x * wr[t].x + v.y * wr[t].y;
+            ay[c] += v.x * wr[t].y - v.y * wr[t].x;
+          }
+        }
+      }
+    }
+    block_sum_nch(ax, ay, red, tid);
+    if (tid < NCH && i0 + tid < ncols) {
+      double sx = 0.0, sy = 0.0;
+#pragma unroll
+      for (int q = 0; q < NT / 64; ++q) {
+        sx += red[q][2 * tid];
+        sy += red[q][2 * tid + 1];
+      }
+      partial[size_t(blockIdx.x) * ldp + i0 + tid] = mk<double>(sx, sy);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(NT) reduce_cols_kernel(const c128* __restrict__ partial, int ldp, unsigned nblk,
+                                                         c128* __restrict__ out) {
+  __shared__ double red[NT / 64][2];
+  const int tid = threadIdx.x, i = blockIdx.x;
+  double sx = 0.0, sy = 0.0;
+  for (unsigned b = tid; b < nblk; b += NT) {
+    const c128 v = partial[size_t(b) * ldp + i];
+    sx += v.x;
+    sy += v.y;
+  }
+  sx = wave_sum(sx);
+  sy = wave_sum(sy);
+  if ((tid & 63) == 0) {
+    red[tid >> 6][0] = sx;
+    red[tid >> 6][1] = sy;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double tx = 0.0, ty = 0.0;
+    for (int q = 0; q < NT / 64; ++q) {
+      tx += red[q][0];
+      ty += red[q][1];
+    }
+    out[i] = mk<double>(tx, ty);
+  }
+}
+
+template <bool DOTS, bool NORM>
+__global__ void __launch_bounds__(NT) update_kernel(const c128* __restrict__ V, size_t ldv, int ncols,
+                                                    const c128* __restrict__ h, c128* __restrict__ w, size_t d,
+                                                    c128* __restrict__ partial, int ldp) {
+  extern __shared__ c128 hs[];
+  __shared__ double red[NT / 64][2 * NCH];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < ncols; i += NT) hs[i] = h[i];
+  __syncthreads();
+  const size_t r0 = static_cast<size_t>(blockIdx.x) * NT * RPT + tid;
+  c128 acc[RPT];
+  bool ok[RPT];
+#pragma unroll
+  for (int t = 0; t < RPT; ++t) {
+    const size_t r = r0 + size_t(t) * NT;
+    ok[t] = r < d;
+    acc[t] = ok[t] ? w[r] : mk<double>(0, 0);
+  }
+  int i = 0;
+  for (; i + 4 <= ncols; i += 4) {
+    c128 v[4][RPT];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) v[u][t] = ok[t] ? V[size_t(i + u) * ldv + r0 + size_t(t) * NT] : mk<double>(0, 0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const c128 hh = hs[i + u];
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) acc[t] = csub(acc[t], cmul(v[u][t], hh));
+    }
+  }
+  for (; i < ncols; ++i) {
+    const c128 hh = hs[i];
+#pragma unroll
+    for (int t = 0; t < RPT; ++t)
+      if (ok[t]) acc[t] = csub(acc[t], cmul(V[size_t(i) * ldv + r0 + size_t(t) * NT], hh));
+  }
+#pragma unroll
+  for (int t = 0; t < RPT; ++t)
+    if (ok[t]) w[r0 + size_t(t) * NT] = acc[t];
+
+  if constexpr (NORM) {
+    double s = 0.0;
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) s += acc[t].x * acc[t].x + acc[t].y * acc[t].y;
+    s = wave_sum(s);
+    if ((tid & 63) == 0) red[tid >> 6][0] = s;
+    __syncthreads();
+    if (tid == 0) {
+      double tot = 0.0;
+      for (int q = 0; q < NT / 64; ++q) tot += red[q][0];
+      partial[blockIdx.x] = mk<double>(tot, 0.0);
+    }
+  }
+  if constexpr (DOTS) {
+    for (int i0 = 0; i0 < ncols; i0 += NCH) {
+      double ax[NCH], ay[NCH];
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        ax[c] = 0.0;
+        ay[c] = 0.0;
+        if (i0 + c < ncols) {
+          const c128* col = V + size_t(i0 + c) * ldv;
+#pragma unroll
+          for (int t = 0; t < RPT; ++t) {
+            if (ok[t]) {
+              const c128 v = col[r0 + size_t(t) * NT];
+              ax[c] += v.x * acc[t].x + v.y * acc[t].y;
+              ay[c] += v.x * acc[t].y - v.y * acc[t].x;
+            }
+          }
+        }
+      }
+      block_sum_nch(ax, ay, red, tid);
+      if (tid < NCH && i0 + tid < ncols) {
+        double sx = 0.0, sy = 0.0;
+#pragma unroll
+        for (int q = 0; q < NT / 64; ++q) {
+          sx += red[q][2 * tid];
+          sy += red[q][2 * tid + 1];
+        }
+        partial[size_t(blockIdx.x) * ldp + i0 + tid] = mk<double>(sx, sy);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void __launch_bounds__(NT) norm2_kernel(const c128* __restrict__ w, size_t d, c128* __restrict__ partial) {
+  __shared__ double red[NT / 64];
+  const int tid = threadIdx.x;
+  const size_t r0 = static_cast<size_t>(blockIdx.x) * NT * RPT + tid;
+  double s = 0.0;
+#pragma unroll
+  for (int t = 0; t < RPT; ++t) {
+    const size_t r = r0 + size_t(t) * NT;
+    if (r < d) {
+      const c128 v = w[r];
+      s += v.x * v.x + v.y * v.y;
+    }
+  }
+  s = wave_sum(s);
+  if ((tid & 63) == 0) red[tid >> 6] = s;
+  __syncthreads();
+  if (tid == 0) {
+    double tot = 0.0;
+    for (int q = 0; q < NT / 64; ++q) tot += red[q];
+    partial[blockIdx.x] = mk<double>(tot, 0.0);
+  }
+}
+
+__global__ void __launch_bounds__(NT) reduce_norm_kernel(const c128* __restrict__ partial, unsigned nblk,
+                                                         double* __restrict__ nrm) {
+  __shared__ double red[NT / 64];
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  for (unsigned b = tid; b < nblk; b += NT) s += partial[b].x;
+  s = wave_sum(s);
+  if ((tid & 63) == 0) red[tid >> 6] = s;
+  __syncthreads();
+  if (tid == 0) {
+    double tot = 0.0;
+    for (int q = 0; q < NT / 64; ++q) tot += red[q];
+    const double n = sqrt(tot);
+    nrm[0] = n;
+    nrm[1] = n > 0.0 ? 1.0 / n : 0.0;
+  }
+}
+
+__global__ void scale_dev_kernel(const c128* __restrict__ in, const double* __restrict__ scale, c128* __restrict__ out,
+                                 size_t d) {
+  const double a = scale[0];
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < d; i += size_t(gridDim.x) * blockDim.x) {
+    const c128 v = in[i];
+    out[i] = mk<double>(v.x * a, v.y * a);
+  }
+}
+
+template <typename Real>
+__global__ void scale_kernel(const cpx<Real>* __restrict__ in, double are, double aim, cpx<Real>* __restrict__ out,
+                             size_t d) {
+  const cpx<Real> a = mk<Real>(static_cast<Real>(are), static_cast<Real>(aim));
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < d; i += size_t(gridDim.x) * blockDim.x)
+    out[i] = cmul(in[i], a);
+}
+
+__global__ void axpy_dev_kernel(const c128* __restrict__ a, const c128* __restrict__ x, c128* __restrict__ y,
+                                size_t d) {
+  const c128 aa = a[0];
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < d; i += size_t(gridDim.x) * blockDim.x)
+    y[i] = csub(y[i], cmul(aa, x[i]));
+}
+
+// Y[r, c] = sum_i V[r, i] Q[i, c] for a block of BR rows staged in LDS
+// (transposed, lds[i*BR + r]); all of a block's rows are read before any is
+// written, so Y may alias V.
+__global__ void __launch_bounds__(NT) basis_gemm_kernel(const c128* __restrict__ V, size_t ldv, int m,
+                                                        const c128* __restrict__ Q, int p, c128* Y, size_t ldy,
+                                                        size_t d, int BR) {
+  extern __shared__ c128 st[];
+  const int tid = threadIdx.x;
+  const size_t r0 = static_cast<size_t>(blockIdx.x) * BR;
+  for (int idx = tid; idx < BR * m; idx += NT) {
+    const int i = idx / BR, r = idx % BR;
+    const size_t row = r0 + r;
+    st[idx] = row < d ? V[size_t(i) * ldv + row] : mk<double>(0, 0);
+  }
+  __syncthreads();
+  for (int o = tid; o < BR * p; o += NT) {
+    const int r = o % BR, c = o / BR;
+    const c128* q = Q + size_t(c) * m;
+    double sx = 0.0, sy = 0.0;
+    for (int i = 0; i < m; ++i) {
+      const c128 a = st[i * BR + r];
+      const c128 b = q[i];
+      sx += a.x * b.x - a.y * b.y;
+      sy += a.x * b.y + a.y * b.x;
+    }
+    const size_t row = r0 + r;
+    if (row < d) Y[size_t(c) * ldy + row] = mk<double>(sx, sy);
+  }
+}
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+__global__ void random_kernel(c128* __restrict__ v, size_t d, unsigned long long seed) {
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < d; i += size_t(gridDim.x) * blockDim.x) {
+    const uint64_t a = splitmix64(seed * 0x100000001B3ull + 2 * i);
+    const uint64_t b = splitmix64(seed * 0x100000001B3ull + 2 * i + 1);
+    const double ua = double(a >> 11) * (1.0 / 9007199254740992.0);
+    const double ub = double(b >> 11) * (1.0 / 9007199254740992.0);
+    v[i] = mk<double>(2.0 * ua - 1.0, 2.0 * ub - 1.0);
+  }
+}
+
+unsigned grid_for(size_t d) {
+  const size_t b = (d + 255) / 256;
+  return static_cast<unsigned>(b < 4096 ? (b ? b : 1) : 4096);
+}
+
+}  // namespace
+
+hipError_t launch_dots(const c128* V, size_t ldv, int ncols, const c128* w, size_t d, c128* partial, int ldp,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(dots_kernel, dim3(row_blocks(d)), dim3(NT), 0, s, V, ldv, ncols, w, d, partial, ldp);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_cols(const c128* partial, int ldp, unsigned nblk, int ncols, c128* out, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_cols_kernel, dim3(ncols), dim3(NT), 0, s, partial, ldp, nblk, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(const c128* V, size_t ldv, int ncols, const c128* h, c128* w, size_t d, hipStream_t s) {
+  hipLaunchKernelGGL((update_kernel<false, false>), dim3(row_blocks(d)), dim3(NT), sizeof(c128) * ncols, s, V, ldv,
+                     ncols, h, w, d, nullptr, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_dots(const c128* V, size_t ldv, int ncols, const c128* h, c128* w, size_t d,
+                              c128* partial, int ldp, hipStream_t s) {
+  hipLaunchKernelGGL((update_kernel<true, false>), dim3(row_blocks(d)), dim3(NT), sizeof(c128) * ncols, s, V, ldv,
+                     ncols, h, w, d, partial, ldp);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_norm2(const c128* V, size_t ldv, int ncols, const c128* h, c128* w, size_t d,
+                               c128* partial, hipStream_t s) {
+  hipLaunchKernelGGL((update_kernel<false, true>), dim3(row_blocks(d)), dim3(NT), sizeof(c128) * ncols, s, V, ldv,
+                     ncols, h, w, d, partial, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm2(const c128* w, size_t d, c128* partial, hipStream_t s) {
+  hipLaunchKernelGGL(norm2_kernel, dim3(row_blocks(d)), dim3(NT), 0, s, w, d, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_norm(const c128* partial, unsigned nblk, double* nrm, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_norm_kernel, dim3(1), dim3(NT), 0, s, partial, nblk, nrm);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_dev(const c128* in, const double* scale, c128* out, size_t d, hipStream_t s) {
+  hipLaunchKernelGGL(scale_dev_kernel, dim3(grid_for(d)), dim3(256), 0, s, in, scale, out, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_c128(const c128* in, double are, double aim, c128* out, size_t d, hipStream_t s) {
+  hipLaunchKernelGGL(scale_kernel<double>, dim3(grid_for(d)), dim3(256), 0, s, in, are, aim, out, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_c64(const c64* in, double are, double aim, c64* out, size_t d, hipStream_t s) {
+  hipLaunchKernelGGL(scale_kernel<float>, dim3(grid_for(d)), dim3(256), 0, s, in, are, aim, out, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_dev(const c128* a, const c128* x, c128* y, size_t d, hipStream_t s) {
+  hipLaunchKernelGGL(axpy_dev_kernel, dim3(grid_for(d)), dim3(256), 0, s, a, x, y, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_basis_gemm(const c128* V, size_t ldv, int m, const c128* Q, int p, c128* Y, size_t ldy, size_t d,
+                             hipStream_t s) {
+  int BR = 64;
+  while (BR > 1 && size_t(BR) * m * sizeof(c128) > 65536) BR >>= 1;
+  const size_t shmem = size_t(BR) * m * sizeof(c128);
+  if (shmem > 65536) return hipErrorInvalidValue;
+  const unsigned grid = static_cast<unsigned>((d + BR - 1) / BR);
+  hipLaunchKernelGGL(basis_gemm_kernel, dim3(grid), dim3(NT), shmem, s, V, ldv, m, Q, p, Y, ldy, d, BR);
+  return hipGetLastError();
+}
+
+hipError_t launch_random(c128* v, size_t d, unsigned long long seed, hipStream_t s) {
+  hipLaunchKernelGGL(random_kernel, dim3(grid_for(d)), dim3(256), 0, s, v, d, seed);
+  return hipGetLastError();
+}
+
+}  // namespace fq

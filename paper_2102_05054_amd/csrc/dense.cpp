@@ -1,0 +1,196 @@
+// Complex Schur decomposition of a small dense matrix: Householder reduction
+// to Hessenberg form, then single-shift QR with Wilkinson shifts and Givens
+// rotations (Golub & Van Loan, Ch. 7), plus adjacent swaps of the triangular
+// factor for reordering.  Used for the m x m Rayleigh quotient of the
+// Krylov-Schur restart (the paper uses ARPACK's implicitly restarted Arnoldi,
+// Sec. 4; Krylov-Schur is an equivalent restart built on this Schur form).
+#include "dense.h"
+
+#include <cmath>
+#include <limits>
+
+namespace fq {
+
+namespace {
+
+// Givens rotation G = [[c, s], [-conj(s), c]] with c real and
+// G [x; y] = [r; 0].
+void givens(zd x, zd y, double* c, zd* s) {
+  const double ax = std::abs(x), ay = std::abs(y);
+  if (ay == 0.0) {
+    *c = 1.0;
+    *s = zd(0, 0);
+    return;
+  }
+  if (ax == 0.0) {
+    *c = 0.0;
+    *s = std::conj(y) / ay;
+    return;
+  }
+  const double r = std::hypot(ax, ay);
+  *c = ax / r;
+  *s = (x / ax) * std::conj(y) / r;
+}
+
+// rows k, k+1 of A, columns [j0, j1):  A <- G A
+void rot_rows(ZMat& A, int k, int j0, int j1, double c, zd s) {
+  for (int j = j0; j < j1; ++j) {
+    const zd a = A(k, j), b = A(k + 1, j);
+    A(k, j) = c * a + s * b;
+    A(k + 1, j) = -std::conj(s) * a + c * b;
+  }
+}
+
+// columns k, k+1 of A, rows [i0, i1):  A <- A G^H
+void rot_cols(ZMat& A, int k, int i0, int i1, double c, zd s) {
+  for (int i = i0; i < i1; ++i) {
+    const zd a = A(i, k), b = A(i, k + 1);
+    A(i, k) = c * a + std::conj(s) * b;
+    A(i, k + 1) = -s * a + c * b;
+  }
+}
+
+void hessenberg(ZMat& A, ZMat& Z) {
+  const int n = A.n;
+  std::vector<zd> v(n);
+  for (int k = 0; k + 2 < n; ++k) {
+    double xn = 0.0;
+    for (int i = k + 1; i < n; ++i) xn += std::norm(A(i, k));
+    xn = std::sqrt(xn);
+    if (xn == 0.0) continue;
+    const zd x0 = A(k + 1, k);
+    const zd ph = std::abs(x0) > 0 ? x0 / std::abs(x0) : zd(1, 0);
+    // v = x + ph*||x|| e1, P = I - 2 v v^H / (v^H v), P x = -ph ||x|| e1
+    for (int i = 0; i < n; ++i) v[i] = 0;
+    for (int i = k + 1; i < n; ++i) v[i] = A(i, k);
+    v[k + 1] += ph * xn;
+    double vn = 0.0;
+    for (int i = k + 1; i < n; ++i) vn += std::norm(v[i]);
+    if (vn == 0.0) continue;
+    const double tau = 2.0 / vn;
+    // A <- P A
+    for (int j = 0; j < n; ++j) {
+      zd s = 0;
+      for (int i = k + 1; i < n; ++i) s += std::conj(v[i]) * A(i, j);
+      s *= tau;
+      for (int i = k + 1; i < n; ++i) A(i, j) -= v[i] * s;
+    }
+    // A <- A P, Z <- Z P
+    for (int i = 0; i < n; ++i) {
+      zd s = 0, t = 0;
+      for (int j = k + 1; j < n; ++j) {
+        s += A(i, j) * v[j];
+        t += Z(i, j) * v[j];
+      }
+      s *= tau;
+      t *= tau;
+      for (int j = k + 1; j < n; ++j) {
+        A(i, j) -= s * std::conj(v[j]);
+        Z(i, j) -= t * std::conj(v[j]);
+      }
+    }
+    for (int i = k + 2; i < n; ++i) A(i, k) = 0;
+  }
+}
+
+}  // namespace
+
+bool schur(ZMat& A, ZMat& Z) {
+  const int n = A.n;
+  Z = ZMat(n, n);
+  for (int i = 0; i < n; ++i) Z(i, i) = 1;
+  if (n <= 1) return true;
+  hessenberg(A, Z);
+  const double eps = std::numeric_limits<double>::epsilon();
+  double anorm = 0.0;
+  for (const zd& x : A.a) anorm = std::max(anorm, std::abs(x));
+  const double tiny = anorm * eps * 1e-3 + std::numeric_limits<double>::min();
+  int hi = n - 1;
+  int iter = 0;
+  const int max_iter = 60 * n;
+  int total = 0;
+  while (hi > 0) {
+    // find the start l of the unreduced block ending at hi
+    int l = hi;
+    while (l > 0) {
+      const double s = std::abs(A(l - 1, l - 1)) + std::abs(A(l, l));
+      if (std::abs(A(l, l - 1)) <= eps * (s > 0 ? s : anorm) || std::abs(A(l, l - 1)) <= tiny) {
+        A(l, l - 1) = 0;
+        break;
+      }
+      --l;
+    }
+    if (l == hi) {
+      --hi;
+      iter = 0;
+      continue;
+    }
+    if (++total > max_iter) return false;
+    ++iter;
+    // Wilkinson shift from the trailing 2x2 of the active block
+    zd mu;
+    if (iter % 11 == 0) {
+      // exceptional shift
+      mu = A(hi, hi) + zd(std::abs(A(hi, hi - 1)) * 0.75, std::abs(A(hi, hi - 1)) * 0.5);
+    } else {
+      const zd a = A(hi - 1, hi - 1), b = A(hi - 1, hi), c = A(hi, hi - 1), d = A(hi, hi);
+      const zd tr = a + d, det = a * d - b * c;
+      const zd disc = std::sqrt(tr * tr * 0.25 - det);
+      const zd e1 = tr * 0.5 + disc, e2 = tr * 0.5 - disc;
+      mu = std::abs(e1 - d) < std::abs(e2 - d) ? e1 : e2;
+    }
+    zd x = A(l, l) - mu, y = A(l + 1, l);
+    for (int k = l; k < hi; ++k) {
+      double c;
+      zd s;
+      givens(x, y, &c, &s);
+      rot_rows(A, k, k > l ? k - 1 : l, n, c, s);
+      rot_cols(A, k, 0, std::min(k + 3, hi + 1), c, s);
+      rot_cols(Z, k, 0, n, c, s);
+      if (k > l) A(k + 1, k - 1) = 0;
+      if (k + 1 < hi) {
+        x = A(k + 1, k);
+        y = A(k + 2, k);
+      }
+    }
+  }
+  for (int j = 0; j < n; ++j)
+    for (int i = j + 1; i < n; ++i) A(i, j) = 0;
+  return true;
+}
+
+void schur_swap(ZMat& T, ZMat& Z, int k) {
+  const int n = T.n;
+  const zd t11 = T(k, k), t22 = T(k + 1, k + 1), t12 = T(k, k + 1);
+  const zd y = t22 - t11;
+  if (std::abs(t12) == 0.0 && std::abs(y) == 0.0) return;
+  double c;
+  zd s;
+  givens(t12, y, &c, &s);
+  rot_rows(T, k, k, n, c, s);
+  rot_cols(T, k, 0, k + 2, c, s);
+  rot_cols(Z, k, 0, n, c, s);
+  T(k, k) = t22;
+  T(k + 1, k + 1) = t11;
+  T(k + 1, k) = 0;
+}
+
+std::vector<zd> tri_eigvec(const ZMat& T, int i) {
+  const int n = T.n;
+  std::vector<zd> y(n, zd(0, 0));
+  y[i] = 1;
+  double tn = 0.0;
+  for (const zd& x : T.a) tn = std::max(tn, std::abs(x));
+  const double small = std::max(tn, 1e-300) * std::numeric_limits<double>::epsilon();
+  const zd lam = T(i, i);
+  for (int j = i - 1; j >= 0; --j) {
+    zd s = 0;
+    for (int l = j + 1; l <= i; ++l) s += T(j, l) * y[l];
+    zd den = T(j, j) - lam;
+    if (std::abs(den) < small) den = small;
+    y[j] = -s / den;
+  }
+  return y;
+}
+
+}  // namespace fq

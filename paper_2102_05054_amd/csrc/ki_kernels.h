@@ -1,0 +1,60 @@
+// Launch interface of the kicked-Ising kernels (library-internal).
+#pragma once
+
+#include "common.h"
+
+namespace fq {
+
+enum : int {
+  KI_PHASE = 1,      // multiply by the diagonal phase table after the first kick
+  KI_ADD_PSI = 2,    // add psi (times psi_coef if KI_PSI_COEF)
+  KI_PSI_COEF = 4,
+  KI_SCALE_IN = 8,   // multiply the loaded tile by in_coef
+};
+
+// Which one-qubit butterflies to apply, split by where the bit lives
+// (see tile_engine.h): register bits of layout A / B, lane bits of A / B.
+struct KickMasks {
+  unsigned regA, laneA, regB, laneB;
+};
+
+template <typename Real>
+struct KiPassArgs {
+  const cpx<Real>* xin;
+  cpx<Real>* xout;
+  const cpx<Real>* psi;
+  const cpx<Real>* tlo;
+  const cpx<Real>* thi;
+  double w;                 // butterfly weight (tan or cot form)
+  double psi_coef_re, psi_coef_im;
+  double in_coef_re, in_coef_im;
+  int n, c, p, m;           // tile bits, chunk bits, position of the high run, table split
+  int flags;
+  KickMasks k1, k2;         // before / after the phase
+};
+
+template <typename Real>
+struct KiSingleArgs {
+  const cpx<Real>* xin;
+  cpx<Real>* xout;
+  const cpx<Real>* psi;
+  const cpx<Real>* tlo;
+  const cpx<Real>* thi;
+  const double2* coefs;     // per-step coefficient of psi, or NULL (= 1)
+  double w;
+  double in_coef_re, in_coef_im;
+  size_t batch_stride;      // amplitudes between problems (blockIdx.x)
+  int L, m, steps, flags;
+  KickMasks kick;
+};
+
+template <typename Real>
+hipError_t ki_launch_pass(const KiPassArgs<Real>& a, int rb, int tb, bool sw, unsigned ntiles, hipStream_t s);
+template <typename Real>
+hipError_t ki_launch_single(const KiSingleArgs<Real>& a, int rb, int tb, bool sw, bool psi_regs,
+                            unsigned nblocks, hipStream_t s);
+
+hipError_t launch_cast_c128_to_c64(const void* in, void* out, size_t n, hipStream_t s);
+hipError_t launch_cast_c64_to_c128(const void* in, void* out, size_t n, hipStream_t s);
+
+}  // namespace fq

@@ -1,0 +1,326 @@
+// Kicked-Ising Floquet passes on gfx950:  U = D K,  K = prod_i exp(-i g X_i).
+//
+// The kick is applied in factored form.  exp(-i g X) = c (1 - i t X) with
+// t = tan g when |tan g| <= 2 ("direct" form: (a, b) -> (a + i w b, b + i w a),
+// w = -t, scale c per site), otherwise exp(-i g X) = (-i s)(X + i u) with
+// u = cot g ("swapped" form: (a, b) -> (b + i w a, a + i w b), w = u, scale
+// -i s per site).  Each output is two FMAs per real component; the product of
+// the per-site scales is folded into the diagonal phase table, which is
+// applied exactly once per U.
+//
+// The diagonal D = exp(-i E(s)) comes from two tables rounded once from FP64:
+//   phase(s) = Tlo[s mod 2^m] * Thi[(s >> m) << 2 | b_0 << 1 | b_{m-1}],
+// Thi also carrying the bonds that cross bit m-1|m and the periodic bond
+// between bits 0 and L-1.
+//
+// Horner step of the geometric sum (Sec. 3, Eq. (geo)):  w <- psi + D K w
+// (the target rotation e^{-i phi} is folded into the tables).  K = K_A K_B for
+// the bits A, B held by two tile shapes; the factors commute and D is
+// diagonal, so a pass over tiles of group S can finish one step and start the
+// next:  K_S -> D -> +psi -> K_S.  Passes alternate between the groups; a
+// prologue applies the other group's kick to psi and the last pass omits the
+// trailing kick.  One pass = one Horner step = read w, read psi, write w.
+#include "tile_engine.h"
+#include "ki_kernels.h"
+
+namespace fq {
+
+template <typename Real, int RB, bool SW>
+__device__ __forceinline__ void kick_regs(cpx<Real> (&v)[1 << RB], unsigned mask, Real w) {
+#pragma unroll
+  for (int i = 0; i < RB; ++i) {
+    if (mask & (1u << i)) {
+#pragma unroll
+      for (int m = 0; m < (1 << RB); ++m) {
+        if (m & (1 << i)) continue;
+        const int m2 = m | (1 << i);
+        const cpx<Real> a = v[m], b = v[m2];
+        if constexpr (SW) {
+          v[m] = xpiwy(b, w, a);
+          v[m2] = xpiwy(a, w, b);
+        } else {
+          v[m] = xpiwy(a, w, b);
+          v[m2] = xpiwy(b, w, a);
+        }
+      }
+    }
+  }
+}
+
+// mask: lane bits (0..5) to butterfly across the wavefront.
+template <typename Real, int RB, bool SW>
+__device__ __forceinline__ void kick_lanes(cpx<Real> (&v)[1 << RB], unsigned mask, Real w) {
+#pragma unroll
+  for (int l = 0; l < 6; ++l) {
+    if (mask & (1u << l)) {
+#pragma unroll
+      for (int m = 0; m < (1 << RB); ++m) {
+        const cpx<Real> p = shfl_xor_c(v[m], 1 << l);
+        if constexpr (SW)
+          v[m] = xpiwy(p, w, v[m]);
+        else
+          v[m] = xpiwy(v[m], w, p);
+      }
+    }
+  }
+}
+
+template <typename Real>
+__device__ __forceinline__ cpx<Real> ki_phase(const cpx<Real>* __restrict__ tlo,
+                                              const cpx<Real>* __restrict__ thi, uint32_t g, int m) {
+  const uint32_t lo = g & ((1u << m) - 1u);
+  const uint32_t hi = ((g >> m) << 2) | ((g & 1u) << 1) | ((g >> (m - 1)) & 1u);
+  return cmul(tlo[lo], thi[hi]);
+}
+
+// ---------------------------------------------------------------------------
+// One pass over all tiles of one group (see ki_kernels.h for the fields).
+// ---------------------------------------------------------------------------
+template <typename Real, int RB, int TB, bool SW>
+__global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
+  using C = cpx<Real>;
+  constexpr int R = 1 << RB;
+  constexpr int T = 1 << TB;
+  extern __shared__ char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int tid = threadIdx.x;
+  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const TileMap tm = make_tile_map(tile, a.n, a.c, a.p);
+  const Real w = static_cast<Real>(a.w);
+
+  C v[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) v[m] = a.xin[tm.g(tid + (m << TB))];
+  if (a.flags & KI_SCALE_IN) {
+    const C s = mk<Real>(static_cast<Real>(a.in_coef_re), static_cast<Real>(a.in_coef_im));
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = cmul(v[m], s);
+  }
+
+  // first kick of this group: A-layout registers and lanes, then B
+  kick_regs<Real, RB, SW>(v, a.k1.regA, w);
+  kick_lanes<Real, RB, SW>(v, a.k1.laneA, w);
+  a_to_b<Real, RB, TB>(v, lds, tid);
+  kick_regs<Real, RB, SW>(v, a.k1.regB, w);
+  kick_lanes<Real, RB, SW>(v, a.k1.laneB, w);
+
+  if (a.flags & (KI_PHASE | KI_ADD_PSI)) {
+    const C pc = mk<Real>(static_cast<Real>(a.psi_coef_re), static_cast<Real>(a.psi_coef_im));
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const uint32_t g = tm.g((tid << RB) + m);
+      C x = v[m];
+      if (a.flags & KI_PHASE) x = cmul(x, ki_phase(a.tlo, a.thi, g, a.m));
+      if (a.flags & KI_ADD_PSI) {
+        const C ps = a.psi[g];
+        x = (a.flags & KI_PSI_COEF) ? cfma(ps, pc, x) : cadd(x, ps);
+      }
+      v[m] = x;
+    }
+  }
+
+  // second kick (starts the next Horner step): B first, then A
+  kick_regs<Real, RB, SW>(v, a.k2.regB, w);
+  kick_lanes<Real, RB, SW>(v, a.k2.laneB, w);
+  if constexpr (RB > 0) __syncthreads();
+  b_to_a<Real, RB, TB>(v, lds, tid);
+  kick_regs<Real, RB, SW>(v, a.k2.regA, w);
+  kick_lanes<Real, RB, SW>(v, a.k2.laneA, w);
+
+#pragma unroll
+  for (int m = 0; m < R; ++m) a.xout[tm.g(tid + (m << TB))] = v[m];
+  (void)T;
+}
+
+// ---------------------------------------------------------------------------
+// Whole state in one workgroup (n = L, or n = 6 with idle lanes for L < 6):
+// all k Horner steps in one launch.  psi stays in registers (layout B) when
+// it fits (PSI_REGS, which also keeps the phases), otherwise both are re-read
+// each step (L1/L2-resident).
+// coefs (device, k entries, may be NULL): coefficient of psi in step s, used
+// for general polynomials; NULL means 1.
+// ---------------------------------------------------------------------------
+template <typename Real, int RB, int TB, bool SW, bool PSI_REGS>
+__global__ void __launch_bounds__(1 << TB) ki_single_kernel(KiSingleArgs<Real> a) {
+  using C = cpx<Real>;
+  constexpr int R = 1 << RB;
+  extern __shared__ char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int tid = threadIdx.x;
+  const Real w = static_cast<Real>(a.w);
+  const uint32_t dim = 1u << a.L;
+  // problem offset for batched launches (one workgroup per problem)
+  const size_t off = static_cast<size_t>(blockIdx.x) * a.batch_stride;
+  const C* __restrict__ psi = a.psi + off;
+  const C* __restrict__ xin = a.xin + off;
+  C* __restrict__ xout = a.xout + off;
+
+  // layout B: tid*R + m
+  C v[R];
+  C ps[PSI_REGS ? R : 1];
+  C ph[PSI_REGS ? R : 1];
+  const bool active = static_cast<uint32_t>(tid << RB) < dim;
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    const uint32_t g = (tid << RB) + m;
+    v[m] = active ? xin[g] : mk<Real>(0, 0);
+    if constexpr (PSI_REGS) {
+      ps[m] = active ? psi[g] : mk<Real>(0, 0);
+      ph[m] = active ? ki_phase(a.tlo, a.thi, g, a.m) : mk<Real>(0, 0);
+    }
+  }
+  if (a.flags & KI_SCALE_IN) {
+    const C s = mk<Real>(static_cast<Real>(a.in_coef_re), static_cast<Real>(a.in_coef_im));
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = cmul(v[m], s);
+  }
+
+  for (int step = 0; step < a.steps; ++step) {
+    kick_regs<Real, RB, SW>(v, a.kick.regB, w);
+    kick_lanes<Real, RB, SW>(v, a.kick.laneB, w);
+    if constexpr (RB > 0) {
+      b_to_a<Real, RB, TB>(v, lds, tid);
+      kick_regs<Real, RB, SW>(v, a.kick.regA, w);
+      kick_lanes<Real, RB, SW>(v, a.kick.laneA, w);
+      __syncthreads();
+      a_to_b<Real, RB, TB>(v, lds, tid);
+      __syncthreads();
+    } else {
+      kick_lanes<Real, RB, SW>(v, a.kick.laneA, w);
+    }
+    C coef = mk<Real>(1, 0);
+    const bool use_coef = a.coefs != nullptr;
+    if (use_coef) {
+      const double2 cc = a.coefs[step];
+      coef = mk<Real>(static_cast<Real>(cc.x), static_cast<Real>(cc.y));
+    }
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      C x;
+      if constexpr (PSI_REGS)
+        x = cmul(v[m], ph[m]);
+      else
+        x = active ? cmul(v[m], ki_phase(a.tlo, a.thi, (tid << RB) + m, a.m)) : v[m];
+      if (a.flags & KI_ADD_PSI) {
+        C p;
+        if constexpr (PSI_REGS)
+          p = ps[m];
+        else
+          p = active ? psi[(tid << RB) + m] : mk<Real>(0, 0);
+        x = use_coef ? cfma(p, coef, x) : cadd(x, p);
+      }
+      v[m] = x;
+    }
+  }
+  if (active) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) xout[(tid << RB) + m] = v[m];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Casts between complex128 and complex64 (mixed-precision filter).
+// ---------------------------------------------------------------------------
+__global__ void cast_c128_to_c64(const c128* __restrict__ in, c64* __restrict__ out, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    out[i] = mk<float>(static_cast<float>(in[i].x), static_cast<float>(in[i].y));
+}
+__global__ void cast_c64_to_c128(const c64* __restrict__ in, c128* __restrict__ out, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    out[i] = mk<double>(in[i].x, in[i].y);
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers: runtime (RB, TB, SW) -> template instance.
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename Real, int RB, int TB, bool SW>
+hipError_t launch_pass_t(const KiPassArgs<Real>& a, unsigned ntiles, hipStream_t s) {
+  const size_t shmem = static_cast<size_t>(lds_slots<RB, TB>()) * sizeof(cpx<Real>);
+  auto kern = ki_pass_kernel<Real, RB, TB, SW>;
+  static bool attr_set = false;
+  if (!attr_set && shmem > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(kern, dim3(ntiles), dim3(1 << TB), shmem, s, a);
+  return hipGetLastError();
+}
+
+template <typename Real, int RB, int TB, bool SW>
+hipError_t launch_single_t(const KiSingleArgs<Real>& a, unsigned nblocks, bool psi_regs, hipStream_t s) {
+  const size_t shmem = static_cast<size_t>(lds_slots<RB, TB>()) * sizeof(cpx<Real>);
+  if (psi_regs) {
+    auto kern = ki_single_kernel<Real, RB, TB, SW, true>;
+    static bool attr_set = false;
+    if (!attr_set && shmem > 65536) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem));
+      if (e != hipSuccess) return e;
+      attr_set = true;
+    }
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(1 << TB), shmem, s, a);
+  } else {
+    auto kern = ki_single_kernel<Real, RB, TB, SW, false>;
+    static bool attr_set = false;
+    if (!attr_set && shmem > 65536) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem));
+      if (e != hipSuccess) return e;
+      attr_set = true;
+    }
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(1 << TB), shmem, s, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+#define FQ_SHAPES(X) X(0, 6) X(1, 6) X(1, 7) X(2, 7) X(2, 8) X(3, 8) X(4, 8) X(5, 8) X(6, 8)
+
+template <typename Real>
+hipError_t ki_launch_pass(const KiPassArgs<Real>& a, int rb, int tb, bool sw, unsigned ntiles, hipStream_t s) {
+#define FQ_CASE(RB_, TB_)                                                  \
+  if (rb == RB_ && tb == TB_)                                              \
+    return sw ? launch_pass_t<Real, RB_, TB_, true>(a, ntiles, s)          \
+              : launch_pass_t<Real, RB_, TB_, false>(a, ntiles, s);
+  FQ_SHAPES(FQ_CASE)
+#undef FQ_CASE
+  return hipErrorInvalidValue;
+}
+
+template <typename Real>
+hipError_t ki_launch_single(const KiSingleArgs<Real>& a, int rb, int tb, bool sw, bool psi_regs,
+                            unsigned nblocks, hipStream_t s) {
+#define FQ_CASE(RB_, TB_)                                                          \
+  if (rb == RB_ && tb == TB_)                                                      \
+    return sw ? launch_single_t<Real, RB_, TB_, true>(a, nblocks, psi_regs, s)     \
+              : launch_single_t<Real, RB_, TB_, false>(a, nblocks, psi_regs, s);
+  FQ_SHAPES(FQ_CASE)
+#undef FQ_CASE
+  return hipErrorInvalidValue;
+}
+
+template hipError_t ki_launch_pass<float>(const KiPassArgs<float>&, int, int, bool, unsigned, hipStream_t);
+template hipError_t ki_launch_pass<double>(const KiPassArgs<double>&, int, int, bool, unsigned, hipStream_t);
+template hipError_t ki_launch_single<float>(const KiSingleArgs<float>&, int, int, bool, bool, unsigned, hipStream_t);
+template hipError_t ki_launch_single<double>(const KiSingleArgs<double>&, int, int, bool, bool, unsigned,
+                                             hipStream_t);
+
+hipError_t launch_cast_c128_to_c64(const void* in, void* out, size_t n, hipStream_t s) {
+  const unsigned blocks = static_cast<unsigned>(std::min<size_t>((n + 255) / 256, 8192));
+  hipLaunchKernelGGL(cast_c128_to_c64, dim3(blocks ? blocks : 1), dim3(256), 0, s,
+                     static_cast<const c128*>(in), static_cast<c64*>(out), n);
+  return hipGetLastError();
+}
+hipError_t launch_cast_c64_to_c128(const void* in, void* out, size_t n, hipStream_t s) {
+  const unsigned blocks = static_cast<unsigned>(std::min<size_t>((n + 255) / 256, 8192));
+  hipLaunchKernelGGL(cast_c64_to_c128, dim3(blocks ? blocks : 1), dim3(256), 0, s,
+                     static_cast<const c64*>(in), static_cast<c128*>(out), n);
+  return hipGetLastError();
+}
+
+}  // namespace fq

@@ -1,0 +1,108 @@
+// The floquet_op object and the library-internal operator interface used by
+// the Krylov driver.
+#pragma once
+
+#include <complex>
+#include <memory>
+#include <vector>
+
+#include "common.h"
+#include "ki_kernels.h"
+
+namespace fq {
+
+using zd = std::complex<double>;
+
+// Device phase tables of the kicked-Ising diagonal for one target rotation.
+struct PhaseTables {
+  double phi = 0.0;
+  c64* tlo32 = nullptr;
+  c64* thi32 = nullptr;
+  c128* tlo64 = nullptr;
+  c128* thi64 = nullptr;
+};
+
+// One tile shape of a multi-pass plan.
+struct KiGroup {
+  int n, c, p, rb, tb;
+  unsigned ntiles;
+  unsigned kbits;  // tile bits the kick acts on
+};
+
+struct KiPlan {
+  bool single = false;
+  int rb = 0, tb = 6;  // single-tile shape
+  int ngroups = 0;
+  KiGroup grp[3];
+};
+
+// Brickwork: per-pass gate program (see bw_kernels.h).
+struct BwProgram;
+
+}  // namespace fq
+
+struct floquet_op {
+  fq_model model;
+  int L;
+  int periodic;
+  std::vector<double> J, h;
+  double g = 0.0;
+  std::vector<fq::zd> gates;  // brickwork, flat as given
+  int device = 0;
+
+  // kicked Ising kick form
+  bool sw = false;
+  double w = 0.0;
+  fq::zd site_scale{1.0, 0.0};
+  int m = 1;  // phase table split
+
+  std::vector<fq::PhaseTables> tables;  // cache, keyed by phi
+  fq::KiPlan plan64, plan128;           // multi-pass plans per dtype
+  int single_max_L64 = 10, single_max_L128 = 10;
+
+  // brickwork device programs (one per dtype), owned
+  std::shared_ptr<fq::BwProgram> bw32, bw64;
+
+  // scratch for the mixed-precision filter and the polynomial coefficients
+  void* psi32 = nullptr;
+  void* out32 = nullptr;
+  double2* coefs_dev = nullptr;
+  size_t coefs_cap = 0;
+
+  // Krylov workspace (complex128): V (d x ncv_cap+1) and helpers
+  void* V = nullptr;
+  int ncv_cap = 0;
+  void* work = nullptr;      // d complex128
+  void* work2 = nullptr;     // d complex128
+  double* dev_small = nullptr;  // reduction scratch
+  size_t dev_small_cap = 0;
+  double* host_small = nullptr; // pinned host mirror
+  size_t host_small_cap = 0;
+
+  size_t dim() const { return size_t(1) << L; }
+};
+
+namespace fq {
+
+// Library-internal entry points shared by the ABI and the Krylov driver.
+fq_status get_tables(floquet_op* op, double phi, const PhaseTables** out);
+fq_status apply_U_internal(floquet_op* op, fq_dtype dt, const void* psi, void* out, hipStream_t s);
+// out = sum_m coef_m ... : geometric sum if coefs == nullptr (rotation phi),
+// otherwise the polynomial with k+1 host coefficients (phi ignored).
+fq_status filter_internal(floquet_op* op, int k, double phi, const zd* coefs, fq_dtype dt,
+                          const void* psi, void* out, hipStream_t s);
+// FP64 state in, FP64 state out, filter arithmetic in dt (casts around it for c64).
+fq_status filter_mixed(floquet_op* op, int k, double phi, fq_dtype dt, const void* psi64, void* out64,
+                       hipStream_t s);
+fq_status ensure_scratch32(floquet_op* op);
+// out = a * psi
+fq_status poly_scale_copy(floquet_op* op, zd a, fq_dtype dt, const void* psi, void* out, hipStream_t s);
+
+// brickwork
+fq_status bw_create(floquet_op* op);
+void bw_destroy(floquet_op* op);
+fq_status bw_apply_U(floquet_op* op, fq_dtype dt, const void* psi, void* out, hipStream_t s);
+fq_status bw_filter(floquet_op* op, int k, double phi, const zd* coefs, fq_dtype dt, const void* psi,
+                    void* out, hipStream_t s);
+
+}  // namespace fq

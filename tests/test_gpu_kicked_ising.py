@@ -1,0 +1,154 @@
+"""GPU parity of the kicked-Ising U pass and the Horner filter against the
+oracle (dense Kronecker U for L <= 12, the oracle's matrix-free U above)."""
+
+import cmath
+import math
+
+import numpy as np
+import pytest
+
+from gpu_util import ki_op, rel, require_gpu, say, to_dev, to_np
+from oracle import filters, models
+from workloads import KickedIsingParams, kicked_ising, random_state
+
+pytestmark = pytest.mark.gpu
+
+# complex128: rounding of O(L) butterflies + phase; complex64: ~sqrt(L) * 2^-24 per U.
+TOL_U = {"c128": 1e-12, "c64": 3e-6}
+
+
+def _dt(name):
+    torch = require_gpu()
+    return torch.complex128 if name == "c128" else torch.complex64
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("L,g,periodic", [
+    (2, 0.9, True), (3, 0.9, False), (5, 1.3, True), (6, 0.9, True), (7, 0.4, False),
+    (8, 1.3, True), (10, 0.9, True), (11, 0.9, True), (12, 1.4, False), (12, 0.9, True),
+])
+def test_apply_U_dense_parity(dt, L, g, periodic):
+    say(f"apply_U dense L={L} g={g} periodic={periodic} {dt}")
+    p = kicked_ising(L, 100 + L, g=g, periodic=periodic)
+    U = models.ki_dense(p)
+    psi = random_state(2 ** L, 7 + L)[0]
+    with ki_op(p) as op:
+        out = to_np(op.apply_U(to_dev(psi, _dt(dt))))
+    assert rel(out, U @ psi) < TOL_U[dt]
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("L", [13, 14, 16, 20])
+def test_apply_U_matrix_free_parity(dt, L):
+    say(f"apply_U matrix-free L={L} {dt}")
+    p = kicked_ising(L, 200 + L)
+    psi = random_state(2 ** L, 9)[0]
+    with ki_op(p) as op:
+        out = to_np(op.apply_U(to_dev(psi, _dt(dt))))
+    assert rel(out, models.ki_apply(p, psi)) < TOL_U[dt]
+
+
+def test_apply_U_in_place_and_norm():
+    torch = require_gpu()
+    p = kicked_ising(16, 5)
+    psi = random_state(2 ** 16, 3)[0]
+    with ki_op(p) as op:
+        x = to_dev(psi, torch.complex128)
+        op.apply_U(x, out=x)
+        out = to_np(x)
+    assert rel(out, models.ki_apply(p, psi)) < 1e-12
+    assert abs(np.linalg.norm(out) - 1) < 1e-12
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("L,g", [(22, 0.9), (25, 0.9)])
+def test_apply_U_large_special_cases(dt, L, g):
+    # Sampled outputs at large L from closed forms: g = 0 gives out = e^{-iE(s)} psi(s);
+    # g = pi/2 gives out(s') = (-i)^L e^{-iE(s')} psi(s) with s' the complement of s.
+    torch = require_gpu()
+    say(f"apply_U special cases L={L} {dt}")
+    rng = np.random.default_rng(L)
+    d = 2 ** L
+    psi = (rng.standard_normal(d) + 1j * rng.standard_normal(d)) / math.sqrt(2 * d)
+    idx = rng.integers(0, d, size=200)
+    tol = TOL_U[dt] * 10
+    for gg in (0.0, math.pi / 2):
+        p = kicked_ising(L, 300 + L, g=gg)
+        with ki_op(p) as op:
+            out = to_np(op.apply_U(to_dev(psi, _dt(dt))))
+        for s in idx:
+            E = 0.0
+            sp = s if gg == 0.0 else (d - 1) ^ s
+            z = [1 - 2 * ((sp >> (L - i)) & 1) for i in range(1, L + 1)]
+            E = sum(p.J[i] * z[i] * z[(i + 1) % L] for i in range(L)) + sum(p.h[i] * z[i] for i in range(L))
+            pref = 1.0 if gg == 0.0 else (-1j) ** L
+            expect = pref * cmath.exp(-1j * E) * psi[s]
+            assert abs(out[sp] - expect) < tol * abs(psi).max() * 10
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("L,k,phi", [(4, 3, 0.3), (6, 0, 1.0), (6, 1, 2.0), (10, 64, 0.0), (11, 17, 4.0),
+                                     (12, 40, 1.1)])
+def test_apply_filter_dense_parity(dt, L, k, phi):
+    say(f"apply_filter dense L={L} k={k} phi={phi} {dt}")
+    p = kicked_ising(L, 400 + L)
+    U = models.ki_dense(p)
+    psi = random_state(2 ** L, 11)[0]
+    ref = filters.geometric_sum(lambda v: U @ v, psi, k, phi)
+    with ki_op(p) as op:
+        out = to_np(op.apply_filter(to_dev(psi, _dt(dt)), k, phi))
+    tol = 1e-12 * (k + 1) if dt == "c128" else 2e-7 * (k + 1) + 2e-6
+    assert rel(out, ref) < tol
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("L,k,phi", [(16, 20, 0.7), (20, 3, 5.0)])
+def test_apply_filter_matrix_free_parity(dt, L, k, phi):
+    say(f"apply_filter matrix-free L={L} k={k} {dt}")
+    p = kicked_ising(L, 500 + L)
+    psi = random_state(2 ** L, 13)[0]
+    ref = filters.geometric_sum(lambda v: models.ki_apply(p, v), psi, k, phi)
+    with ki_op(p) as op:
+        out = to_np(op.apply_filter(to_dev(psi, _dt(dt)), k, phi))
+    tol = 1e-12 * (k + 1) if dt == "c128" else 2e-7 * (k + 1) + 2e-6
+    assert rel(out, ref) < tol
+
+
+@pytest.mark.parametrize("L", [8, 12])
+def test_apply_polynomial_parity(L):
+    torch = require_gpu()
+    p = kicked_ising(L, 600 + L)
+    U = models.ki_dense(p)
+    rng = np.random.default_rng(L)
+    coeffs = rng.standard_normal(9) + 1j * rng.standard_normal(9)
+    psi = random_state(2 ** L, 17)[0]
+    ref = filters.polynomial(lambda v: U @ v, psi, list(coeffs))
+    with ki_op(p) as op:
+        out = to_np(op.apply_polynomial(to_dev(psi, torch.complex128), coeffs))
+        out0 = to_np(op.apply_polynomial(to_dev(psi, torch.complex128), coeffs[:1]))
+    assert rel(out, ref) < 1e-11
+    assert rel(out0, coeffs[0] * psi) < 1e-15
+
+
+def test_filter_eigenvector_closed_form():
+    # g_k(U) v = g_k(omega) v for an eigenvector (Eq. (gkmapping)).
+    torch = require_gpu()
+    from oracle import eig
+    p = kicked_ising(10, 77)
+    U = models.ki_dense(p)
+    om, V = eig.full_closest(U, 3, 0.5)
+    with ki_op(p) as op:
+        for n in range(3):
+            out = to_np(op.apply_filter(to_dev(V[:, n], torch.complex128), 50, 0.5))
+            lam = filters.gk_scalar(np.array([om[n]]), 50, 0.5)[0]
+            assert np.linalg.norm(out - lam * V[:, n]) < 1e-10 * abs(lam)
+
+
+def test_determinism_bitwise():
+    torch = require_gpu()
+    p = kicked_ising(18, 3)
+    psi = to_dev(random_state(2 ** 18, 1)[0], torch.complex64)
+    with ki_op(p) as op:
+        a = to_np(op.apply_filter(psi, 30, 0.2))
+        b = to_np(op.apply_filter(psi, 30, 0.2))
+    assert np.array_equal(a, b)
