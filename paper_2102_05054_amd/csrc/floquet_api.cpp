@@ -115,18 +115,16 @@ void free_tables(PhaseTables& t) {
 // Tile shapes and plans
 // ---------------------------------------------------------------------------
 
-// (RB, TB) for a tile of n bits: as many threads as possible (<= 256) while
-// every bit stays reachable (RB <= 6, TB <= RB + 6).
+// (RB, TB) for a tile of n <= 13 bits: at most 16 amplitudes per thread
+// (RB <= 4), up to 512 threads, every bit reachable (TB <= RB + 6).
 void tile_shape(int n, int* rb, int* tb) {
   if (n <= 6) {
     *tb = 6;
     *rb = 0;
     return;
   }
-  int t = std::min(8, (n + 6) / 2);
-  t = std::max(6, t);
-  *tb = t;
-  *rb = n - t;
+  *rb = std::min(4, n - 6);
+  *tb = n - *rb;
 }
 
 KickMasks masks_for(unsigned kbits, int n, int rb, int tb) {
@@ -147,8 +145,11 @@ KickMasks masks_for(unsigned kbits, int n, int rb, int tb) {
 
 KiPlan make_plan(int L, bool c64_dt) {
   KiPlan pl;
-  const int c = c64_dt ? 3 : 2;
-  const int nmax = c64_dt ? 14 : 13;
+  // chunk of contiguous amplitudes in the high-bit tiles: 64 bytes, or 32
+  // bytes when that keeps both tiles at <= 13 bits (<= 512 threads)
+  int c = c64_dt ? 3 : 2;
+  if (c64_dt && L + 3 > 26 && L + 2 <= 26) c = 2;
+  const int nmax = 13;
   if (L + c <= 2 * nmax) {
     const int tot = L + c;
     const int nlo = (tot + 1) / 2;
@@ -195,7 +196,7 @@ KiPlan make_plan(int L, bool c64_dt) {
   return pl;
 }
 
-bool single_ok(int L, bool c64_dt) { return L <= (c64_dt ? 14 : 13); }
+bool single_ok(int L, bool) { return L <= 13; }
 
 // ---------------------------------------------------------------------------
 // Kicked-Ising launches
@@ -249,7 +250,7 @@ template <typename Real>
 fq_status ki_pass(floquet_op* op, const KiGroup& gp, const PhaseTables* tab, const void* xin, void* xout,
                   const void* psi, int flags, bool k2, zd psi_coef, zd in_coef, hipStream_t s) {
   // a tile must cover every thread of the workgroup and stay inside the state
-  if (gp.n < gp.tb || gp.rb + gp.tb != gp.n || gp.rb > 6 || gp.tb > gp.rb + 6 || gp.n > op->L ||
+  if (gp.n < gp.tb || gp.rb + gp.tb != gp.n || gp.rb > 4 || gp.tb > 9 || gp.tb > gp.rb + 6 || gp.n > op->L ||
       (size_t(gp.ntiles) << gp.n) != op->dim()) {
     set_error("internal: inconsistent kicked-Ising tile plan");
     return FQ_EINVAL;

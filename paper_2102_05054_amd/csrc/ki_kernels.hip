@@ -80,56 +80,68 @@ template <typename Real, int RB, int TB, bool SW>
 __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
   using C = cpx<Real>;
   constexpr int R = 1 << RB;
-  constexpr int T = 1 << TB;
   extern __shared__ char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
   const int tid = threadIdx.x;
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const TileMap tm = make_tile_map(tile, a.n, a.c, a.p);
   const Real w = static_cast<Real>(a.w);
+  const bool do_ph = (a.flags & KI_PHASE) != 0;
+  const bool do_ps = (a.flags & KI_ADD_PSI) != 0;
 
-  C v[R];
+  // The tile and psi are read in layout A (consecutive lanes <-> consecutive
+  // addresses) at the start; the phase and +psi are applied in layout A too,
+  // so every global access of the pass is coalesced.
+  C v[R], ps[R];
 #pragma unroll
   for (int m = 0; m < R; ++m) v[m] = a.xin[tm.g(tid + (m << TB))];
+  if (do_ps) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) ps[m] = a.psi[tm.g(tid + (m << TB))];
+  }
   if (a.flags & KI_SCALE_IN) {
     const C s = mk<Real>(static_cast<Real>(a.in_coef_re), static_cast<Real>(a.in_coef_im));
 #pragma unroll
     for (int m = 0; m < R; ++m) v[m] = cmul(v[m], s);
   }
 
-  // first kick of this group: A-layout registers and lanes, then B
+  // first kick of this group: layout A, then layout B, back to A
   kick_regs<Real, RB, SW>(v, a.k1.regA, w);
   kick_lanes<Real, RB, SW>(v, a.k1.laneA, w);
-  a_to_b<Real, RB, TB>(v, lds, tid);
-  kick_regs<Real, RB, SW>(v, a.k1.regB, w);
-  kick_lanes<Real, RB, SW>(v, a.k1.laneB, w);
+  if (a.k1.regB | a.k1.laneB) {
+    a_to_b<Real, RB, TB>(v, lds, tid);
+    kick_regs<Real, RB, SW>(v, a.k1.regB, w);
+    kick_lanes<Real, RB, SW>(v, a.k1.laneB, w);
+    if constexpr (RB > 0) __syncthreads();
+    b_to_a<Real, RB, TB>(v, lds, tid);
+  }
 
-  if (a.flags & (KI_PHASE | KI_ADD_PSI)) {
+  if (do_ph || do_ps) {
     const C pc = mk<Real>(static_cast<Real>(a.psi_coef_re), static_cast<Real>(a.psi_coef_im));
+    const bool coef = (a.flags & KI_PSI_COEF) != 0;
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-      const uint32_t g = tm.g((tid << RB) + m);
       C x = v[m];
-      if (a.flags & KI_PHASE) x = cmul(x, ki_phase(a.tlo, a.thi, g, a.m));
-      if (a.flags & KI_ADD_PSI) {
-        const C ps = a.psi[g];
-        x = (a.flags & KI_PSI_COEF) ? cfma(ps, pc, x) : cadd(x, ps);
-      }
+      if (do_ph) x = cmul(x, ki_phase(a.tlo, a.thi, tm.g(tid + (m << TB)), a.m));
+      if (do_ps) x = coef ? cfma(ps[m], pc, x) : cadd(x, ps[m]);
       v[m] = x;
     }
   }
 
-  // second kick (starts the next Horner step): B first, then A
-  kick_regs<Real, RB, SW>(v, a.k2.regB, w);
-  kick_lanes<Real, RB, SW>(v, a.k2.laneB, w);
-  if constexpr (RB > 0) __syncthreads();
-  b_to_a<Real, RB, TB>(v, lds, tid);
+  // second kick (starts the next Horner step): layout A, then B, back to A
   kick_regs<Real, RB, SW>(v, a.k2.regA, w);
   kick_lanes<Real, RB, SW>(v, a.k2.laneA, w);
+  if (a.k2.regB | a.k2.laneB) {
+    if constexpr (RB > 0) __syncthreads();
+    a_to_b<Real, RB, TB>(v, lds, tid);
+    kick_regs<Real, RB, SW>(v, a.k2.regB, w);
+    kick_lanes<Real, RB, SW>(v, a.k2.laneB, w);
+    if constexpr (RB > 0) __syncthreads();
+    b_to_a<Real, RB, TB>(v, lds, tid);
+  }
 
 #pragma unroll
   for (int m = 0; m < R; ++m) a.xout[tm.g(tid + (m << TB))] = v[m];
-  (void)T;
 }
 
 // ---------------------------------------------------------------------------
@@ -279,7 +291,7 @@ hipError_t launch_single_t(const KiSingleArgs<Real>& a, unsigned nblocks, bool p
 
 }  // namespace
 
-#define FQ_SHAPES(X) X(0, 6) X(1, 6) X(1, 7) X(2, 7) X(2, 8) X(3, 8) X(4, 8) X(5, 8) X(6, 8)
+#define FQ_SHAPES(X) X(0, 6) X(1, 6) X(2, 6) X(3, 6) X(4, 6) X(4, 7) X(4, 8) X(4, 9)
 
 template <typename Real>
 hipError_t ki_launch_pass(const KiPassArgs<Real>& a, int rb, int tb, bool sw, unsigned ntiles, hipStream_t s) {

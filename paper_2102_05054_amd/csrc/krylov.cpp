@@ -22,6 +22,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -35,6 +37,15 @@
 namespace fq {
 
 namespace {
+
+// FQ_VERBOSE=1 in the environment prints one line per restart cycle to stderr.
+bool verbose() {
+  static const bool v = [] {
+    const char* e = std::getenv("FQ_VERBOSE");
+    return e && e[0] && e[0] != '0';
+  }();
+  return v;
+}
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -224,132 +235,170 @@ struct Solver {
   // Krylov-Schur run in arithmetic dt from the (normalised) start vector in
   // V[:, 0].  Stops when all nev wanted Ritz estimates are below
   // tolg*|theta| and, if check_true, the FP64 residuals are below tol.
-  fq_status run(fq_dtype dt, double tolg, double tol, bool check_true, int restart_budget, PhaseResult* res) {
+  // With `early`, the projected matrix is also analysed every few steps
+  // inside a cycle (a warm start reaches convergence after ~nev steps).
+  fq_status run(fq_dtype dt, double tolg, double tol, bool check_true, int restart_budget, bool early,
+                PhaseResult* res) {
     const int m = ncv;
     ZMat H(m + 1, m);
     int kk = 0;
     const int p_keep = std::min(m - 1, std::max(nev + 1, nev + (m - nev) / 2));
+    const int check_every = std::max(4, m / 16);
     double best = 1e300;
     int stall = 0;
     for (;;) {
-      // extend the decomposition from kk to m columns
       const double t0 = now_s();
-      for (int j = kk; j < m; ++j) FQ_TRY(arnoldi_step(op, ws, j, k, phi, dt, s));
-      if (m > kk) {
-        const size_t bytes = size_t(m - kk) * ws.slot_doubles * sizeof(double);
-        FQ_HIP_CHECK(hipMemcpyAsync(ws.hslots + size_t(kk) * ws.slot_doubles, ws.slots + size_t(kk) * ws.slot_doubles,
-                                    bytes, hipMemcpyDeviceToHost, s));
-      }
-      FQ_HIP_CHECK(hipStreamSynchronize(s));
-      const double t1 = now_s();
-      t_filter += t1 - t0;  // filter + orthogonalisation (stream-ordered)
-      st->n_filter_apps += m - kk;
-      st->n_U_apps += (long long)(m - kk) * k;
-      if (dt == FQ_C64) st->n_U_apps_c64 += (long long)(m - kk) * k;
-      double hn = 0.0;
+      int copied = kk;  // columns of H already on the host
       for (int j = kk; j < m; ++j) {
-        const double* sl = ws.hslots + size_t(j) * ws.slot_doubles;
-        for (int i = 0; i <= j; ++i) {
-          H(i, j) = zd(sl[2 * i] + sl[2 * (ws.ncv + 1) + 2 * i], sl[2 * i + 1] + sl[2 * (ws.ncv + 1) + 2 * i + 1]);
-          hn = std::max(hn, std::abs(H(i, j)));
+        FQ_TRY(arnoldi_step(op, ws, j, k, phi, dt, s));
+        st->n_filter_apps += 1;
+        st->n_U_apps += k;
+        if (dt == FQ_C64) st->n_U_apps_c64 += k;
+        const int mm = j + 1;
+        const bool full = mm == m;
+        const bool probe = early && mm >= nev + 2 && ((mm - nev - 2) % check_every == 0);
+        if (!full && !probe) continue;
+        const size_t bytes = size_t(mm - copied) * ws.slot_doubles * sizeof(double);
+        FQ_HIP_CHECK(hipMemcpyAsync(ws.hslots + size_t(copied) * ws.slot_doubles,
+                                    ws.slots + size_t(copied) * ws.slot_doubles, bytes, hipMemcpyDeviceToHost, s));
+        FQ_HIP_CHECK(hipStreamSynchronize(s));
+        double hn = 0.0;
+        for (int jj = copied; jj < mm; ++jj) {
+          const double* sl = ws.hslots + size_t(jj) * ws.slot_doubles;
+          for (int i = 0; i <= jj; ++i) {
+            H(i, jj) = zd(sl[2 * i] + sl[2 * (ws.ncv + 1) + 2 * i], sl[2 * i + 1] + sl[2 * (ws.ncv + 1) + 2 * i + 1]);
+            hn = std::max(hn, std::abs(H(i, jj)));
+          }
+          const double beta = sl[4 * (ws.ncv + 1)];
+          if (!std::isfinite(beta) || !std::isfinite(hn)) {
+            set_error("non-finite value in the Arnoldi process (filter output overflow?)");
+            return FQ_ENUMERIC;
+          }
+          if (beta <= 1e-14 * std::max(hn, 1e-300)) {
+            set_error("Arnoldi breakdown: the Krylov space became invariant before ncv vectors");
+            return FQ_ENUMERIC;
+          }
+          H(jj + 1, jj) = beta;
         }
-        const double beta = sl[4 * (ws.ncv + 1)];
-        if (!std::isfinite(beta) || !std::isfinite(hn)) {
-          set_error("non-finite value in the Arnoldi process (filter output overflow?)");
-          return FQ_ENUMERIC;
+        copied = mm;
+        const double t1 = now_s();
+        t_filter += t1 - t0;
+        // analyse the decomposition of size mm
+        ZMat T, Z, X;
+        std::vector<zd> bz;
+        int nconv = 0;
+        double worst = 0.0;
+        FQ_TRY(analyse(H, mm, std::max(p_keep, nev), tolg, &T, &Z, &bz, &X, &nconv, &worst));
+        if (verbose())
+          std::fprintf(stderr,
+                       "[fq] %s cycle %d: size %d (from %d) %.3fs, nconv %d/%d, worst rel est %.3e, |theta| %.4g..%.4g\n",
+                       dt == FQ_C64 ? "c64" : "c128", res->restarts, mm, kk, t1 - t0, nconv, nev, worst,
+                       std::abs(T(0, 0)), std::abs(T(nev - 1, nev - 1)));
+        const bool all = nconv >= nev;
+        if (!full) {
+          if (!all) continue;  // keep extending this cycle
+          FQ_TRY(ritz_and_residuals(op, ws, mm, X, nev, &res->ritz, s, &st->n_U_apps));
+          double rmax = 0.0;
+          for (double r : res->ritz.resid) rmax = std::max(rmax, r);
+          if (!check_true || rmax <= tol) {
+            res->converged = true;
+            return FQ_OK;
+          }
+          continue;
         }
-        if (beta <= 1e-14 * std::max(hn, 1e-300)) {
-          set_error("Arnoldi breakdown: the Krylov space became invariant before ncv vectors");
-          return FQ_ENUMERIC;
+        const bool out_of_budget = res->restarts >= restart_budget;
+        if (worst < 0.5 * best) {
+          best = worst;
+          stall = 0;
+        } else {
+          ++stall;
         }
-        H(j + 1, j) = beta;
-      }
-      // Schur form of S = H[0:m, 0:m], wanted = largest |theta| first
-      const double t2 = now_s();
-      ZMat T(m, m), Z;
-      for (int j = 0; j < m; ++j)
-        for (int i = 0; i < m; ++i) T(i, j) = H(i, j);
-      if (!schur(T, Z)) {
-        set_error("QR iteration on the projected matrix did not converge");
-        return FQ_ENUMERIC;
-      }
-      schur_sort(T, Z, std::max(p_keep, nev), [](const zd& a, const zd& b) { return std::abs(a) > std::abs(b); });
-      // b^T Z
-      std::vector<zd> bz(m, zd(0, 0));
-      for (int c = 0; c < m; ++c) {
-        zd acc = 0;
-        for (int i = 0; i < m; ++i) acc += H(m, i) * Z(i, c);
-        bz[c] = acc;
-      }
-      // Ritz estimates of the wanted pairs
-      int nconv = 0;
-      double worst = 0.0;
-      ZMat X(m, nev);
-      for (int i = 0; i < nev; ++i) {
-        std::vector<zd> y = tri_eigvec(T, i);
-        double yn = 0.0;
-        for (const zd& v : y) yn += std::norm(v);
-        yn = std::sqrt(yn);
-        zd e = 0;
-        for (int l = 0; l <= i; ++l) e += bz[l] * y[l];
-        const double est = std::abs(e) / (yn * std::max(std::abs(T(i, i)), 1e-300));
-        worst = std::max(worst, est);
-        if (est <= tolg) ++nconv;
-        for (int r = 0; r < m; ++r) {
-          zd acc = 0;
-          for (int l = 0; l <= i; ++l) acc += Z(r, l) * y[l];
-          X(r, i) = acc / yn;
+        // complex64 phase: stop once the estimates sit at the complex64 floor
+        // (no longer halving) -- not while they are still far above it
+        const bool stalled = !check_true && stall >= 3 && worst < 1e-3;
+        if (all || out_of_budget || stalled) {
+          FQ_TRY(ritz_and_residuals(op, ws, m, X, nev, &res->ritz, s, &st->n_U_apps));
+          double rmax = 0.0;
+          for (double r : res->ritz.resid) rmax = std::max(rmax, r);
+          if (!check_true) {
+            res->converged = all;
+            return FQ_OK;
+          }
+          if (rmax <= tol) {
+            res->converged = true;
+            return FQ_OK;
+          }
+          if (out_of_budget) {
+            res->converged = false;
+            return FQ_OK;
+          }
+          tolg *= 0.1;  // the estimates were optimistic: tighten and continue
         }
-      }
-      t_restart += now_s() - t2;
-      const bool all = nconv >= nev;
-      const bool out_of_budget = res->restarts >= restart_budget;
-      if (worst < 0.5 * best) {
-        best = worst;
-        stall = 0;
-      } else {
-        ++stall;
-      }
-      const bool stalled = !check_true && stall >= 3;
-      if (all || out_of_budget || stalled) {
-        FQ_TRY(ritz_and_residuals(op, ws, m, X, nev, &res->ritz, s, &st->n_U_apps));
-        double rmax = 0.0;
-        for (double r : res->ritz.resid) rmax = std::max(rmax, r);
-        if (!check_true) {
-          res->converged = all;
-          return FQ_OK;
+        // restart: keep p_keep Schur vectors
+        const double t3 = now_s();
+        const int p = p_keep;
+        std::vector<c128> q(size_t(m) * p);
+        for (int c = 0; c < p; ++c)
+          for (int i = 0; i < m; ++i) q[size_t(c) * m + i] = mk<double>(Z(i, c).real(), Z(i, c).imag());
+        FQ_HIP_CHECK(hipMemcpyAsync(ws.qbuf, q.data(), q.size() * sizeof(c128), hipMemcpyHostToDevice, s));
+        FQ_HIP_CHECK(launch_basis_gemm(ws.V, ws.d, m, ws.qbuf, p, ws.V, ws.d, ws.d, s));
+        FQ_HIP_CHECK(hipMemcpyAsync(ws.V + size_t(p) * ws.d, ws.V + size_t(m) * ws.d, ws.d * sizeof(c128),
+                                    hipMemcpyDeviceToDevice, s));
+        ZMat Hn(m + 1, m);
+        for (int jj = 0; jj < p; ++jj) {
+          for (int i = 0; i <= jj; ++i) Hn(i, jj) = T(i, jj);
+          Hn(p, jj) = bz[jj];
         }
-        if (rmax <= tol) {
-          res->converged = true;
-          return FQ_OK;
-        }
-        if (out_of_budget) {
-          res->converged = false;
-          return FQ_OK;
-        }
-        tolg *= 0.1;  // the estimates were optimistic: tighten and continue
+        H = Hn;
+        kk = p;
+        ++res->restarts;
+        FQ_HIP_CHECK(hipStreamSynchronize(s));
+        t_restart += now_s() - t3;
       }
-      // restart: keep p_keep Schur vectors
-      const double t3 = now_s();
-      const int p = p_keep;
-      std::vector<c128> q(size_t(m) * p);
-      for (int c = 0; c < p; ++c)
-        for (int i = 0; i < m; ++i) q[size_t(c) * m + i] = mk<double>(Z(i, c).real(), Z(i, c).imag());
-      FQ_HIP_CHECK(hipMemcpyAsync(ws.qbuf, q.data(), q.size() * sizeof(c128), hipMemcpyHostToDevice, s));
-      FQ_HIP_CHECK(launch_basis_gemm(ws.V, ws.d, m, ws.qbuf, p, ws.V, ws.d, ws.d, s));
-      FQ_HIP_CHECK(hipMemcpyAsync(ws.V + size_t(p) * ws.d, ws.V + size_t(m) * ws.d, ws.d * sizeof(c128),
-                                  hipMemcpyDeviceToDevice, s));
-      ZMat Hn(m + 1, m);
-      for (int j = 0; j < p; ++j) {
-        for (int i = 0; i <= j; ++i) Hn(i, j) = T(i, j);
-        Hn(p, j) = bz[j];
-      }
-      H = Hn;
-      kk = p;
-      ++res->restarts;
-      FQ_HIP_CHECK(hipStreamSynchronize(s));
-      t_restart += now_s() - t3;
     }
+  }
+
+  // Schur form of S = H[0:mm, 0:mm] with the nsort largest |theta| first,
+  // b^T Z, and the Ritz coefficient vectors / relative estimates of the nev
+  // wanted pairs.
+  fq_status analyse(const ZMat& H, int mm, int nsort, double tolg, ZMat* T, ZMat* Z, std::vector<zd>* bz, ZMat* X,
+                    int* nconv, double* worst) {
+    const double t2 = now_s();
+    *T = ZMat(mm, mm);
+    for (int j = 0; j < mm; ++j)
+      for (int i = 0; i < mm; ++i) (*T)(i, j) = H(i, j);
+    if (!schur(*T, *Z)) {
+      set_error("QR iteration on the projected matrix did not converge");
+      return FQ_ENUMERIC;
+    }
+    schur_sort(*T, *Z, std::min(nsort, mm), [](const zd& a, const zd& b) { return std::abs(a) > std::abs(b); });
+    bz->assign(mm, zd(0, 0));
+    for (int c = 0; c < mm; ++c) {
+      zd acc = 0;
+      for (int i = 0; i < mm; ++i) acc += H(mm, i) * (*Z)(i, c);
+      (*bz)[c] = acc;
+    }
+    *nconv = 0;
+    *worst = 0.0;
+    *X = ZMat(mm, nev);
+    for (int i = 0; i < nev; ++i) {
+      std::vector<zd> y = tri_eigvec(*T, i);
+      double yn = 0.0;
+      for (const zd& v : y) yn += std::norm(v);
+      yn = std::sqrt(yn);
+      zd e = 0;
+      for (int l = 0; l <= i; ++l) e += (*bz)[l] * y[l];
+      const double est = std::abs(e) / (yn * std::max(std::abs((*T)(i, i)), 1e-300));
+      *worst = std::max(*worst, est);
+      if (est <= tolg) ++*nconv;
+      for (int r = 0; r < mm; ++r) {
+        zd acc = 0;
+        for (int l = 0; l <= i; ++l) acc += (*Z)(r, l) * y[l];
+        (*X)(r, i) = acc / yn;
+      }
+    }
+    t_restart += now_s() - t2;
+    return FQ_OK;
   }
 };
 
@@ -426,11 +475,11 @@ fq_status arnoldi_solve(floquet_op* op, int nev, double phi, const fq_arnoldi_op
   fq_status status = FQ_OK;
   const bool mixed = o->filter_dtype == FQ_C64;
   if (!mixed) {
-    FQ_TRY(sv.run(FQ_C128, 0.5 * o->tol, o->tol, true, o->max_restarts, &res));
+    FQ_TRY(sv.run(FQ_C128, 0.5 * o->tol, o->tol, true, o->max_restarts, false, &res));
   } else {
     // complex64 phase: converge the Ritz estimates to the c64 level
     const double tol32 = std::max(o->tol, 2e-6);
-    FQ_TRY(sv.run(FQ_C64, tol32, o->tol, false, o->max_restarts, &res));
+    FQ_TRY(sv.run(FQ_C64, tol32, o->tol, false, o->max_restarts, false, &res));
     double rmax = 0.0;
     for (double r : res.ritz.resid) rmax = std::max(rmax, r);
     if (o->refine && rmax > o->tol) {
@@ -451,7 +500,7 @@ fq_status arnoldi_solve(floquet_op* op, int nev, double phi, const fq_arnoldi_op
       PhaseResult res2;
       res2.restarts = 0;
       const int budget = std::max(0, o->max_restarts - res.restarts);
-      FQ_TRY(sv.run(FQ_C128, 0.5 * o->tol, o->tol, true, budget, &res2));
+      FQ_TRY(sv.run(FQ_C128, 0.5 * o->tol, o->tol, true, budget, true, &res2));
       res2.restarts += res.restarts;
       res = res2;
       st->t_refine = now_s() - t_ref0;
