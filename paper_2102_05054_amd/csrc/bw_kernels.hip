@@ -1,18 +1,431 @@
 // Brickwork random-circuit passes (Sec. 2, Eq. (U), Eq. (unitary)).
+//
+// U = U_a U_b with U_b acting first.  Cutting the chain at an even site c_s,
+// the gates split into a right block on sites c_s..L (U_b's gates from
+// (c_s, c_s+1) on, then U_a's gates right of c_s) and a left block on sites
+// 1..c_s; the right block's U_a gates commute with the left block's U_b
+// gates, so U = U_L U_R with U_R first -- the light-cone split behind the
+// paper's two-GEMM product (Eq. (matvec)), used here as two tile passes.
+//   right pass: tile = global bits [0, L - c_s], contiguous;
+//   left pass:  tile = a chunk of low bits + global bits [L - c_s, L),
+//               then e^{-i phi} and +psi for the Horner step.
+// One Horner step = right pass (read w, write w) + left pass (read w, read
+// psi, write w).  Inside a tile the gates are applied layer by layer in
+// windows of up to four consecutive tile bits: each thread takes the 16
+// amplitudes of one window group from LDS into registers, applies every gate
+// of the layer that lies in the window, and writes them back.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "bw_kernels.h"
 #include "op.h"
 
 namespace fq {
 
-struct BwProgram {};
+namespace {
 
-fq_status bw_create(floquet_op*) {
-  set_error("brickwork model: kernels not built in this version");
-  return FQ_EINVAL;
+constexpr int BW_TB = 8;  // 256 threads
+constexpr int BW_T = 1 << BW_TB;
+
+__device__ __forceinline__ int bw_phys(int j) { return j + (j >> 4); }
+
+// 4x4 gate on local bits (L0, L0+1) of a window of WB bits
+template <typename Real, int WB, int L0>
+__device__ __forceinline__ void gate2(cpx<Real> (&v)[1 << WB], const c128* __restrict__ M) {
+  cpx<Real> m[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) m[i] = mk<Real>(static_cast<Real>(M[i].x), static_cast<Real>(M[i].y));
+  constexpr int lo = 1 << L0, hi = 1 << (L0 + 1);
+#pragma unroll
+  for (int base = 0; base < (1 << WB); ++base) {
+    if (base & (lo | hi)) continue;
+    const int idx[4] = {base, base | lo, base | hi, base | hi | lo};  // local index 2*b_hi + b_lo
+    cpx<Real> a[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a[c] = v[idx[c]];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      cpx<Real> acc = cmul(m[4 * r], a[0]);
+#pragma unroll
+      for (int c = 1; c < 4; ++c) acc = cfma(m[4 * r + c], a[c], acc);
+      v[idx[r]] = acc;
+    }
+  }
 }
-void bw_destroy(floquet_op*) {}
-fq_status bw_apply_U(floquet_op*, fq_dtype, const void*, void*, hipStream_t) { return FQ_EINVAL; }
-fq_status bw_filter(floquet_op*, int, double, const zd*, fq_dtype, const void*, void*, hipStream_t) {
-  return FQ_EINVAL;
+
+template <typename Real, int WB, int L0>
+__device__ __forceinline__ void gate1(cpx<Real> (&v)[1 << WB], const c128* __restrict__ M) {
+  const cpx<Real> m00 = mk<Real>(static_cast<Real>(M[0].x), static_cast<Real>(M[0].y));
+  const cpx<Real> m01 = mk<Real>(static_cast<Real>(M[1].x), static_cast<Real>(M[1].y));
+  const cpx<Real> m10 = mk<Real>(static_cast<Real>(M[2].x), static_cast<Real>(M[2].y));
+  const cpx<Real> m11 = mk<Real>(static_cast<Real>(M[3].x), static_cast<Real>(M[3].y));
+  constexpr int bit = 1 << L0;
+#pragma unroll
+  for (int base = 0; base < (1 << WB); ++base) {
+    if (base & bit) continue;
+    const cpx<Real> a = v[base], b = v[base | bit];
+    v[base] = cfma(m01, b, cmul(m00, a));
+    v[base | bit] = cfma(m11, b, cmul(m10, a));
+  }
+}
+
+template <typename Real, int WB>
+__device__ __forceinline__ void apply_gate(cpx<Real> (&v)[1 << WB], int kind, int l, const c128* M) {
+  // kind 2: two-site gate on local bits (l, l+1); kind 1: one-site gate on l
+  if (kind == 2) {
+    if (l == 0) gate2<Real, WB, 0>(v, M);
+    if constexpr (WB >= 3)
+      if (l == 1) gate2<Real, WB, 1>(v, M);
+    if constexpr (WB >= 4)
+      if (l == 2) gate2<Real, WB, 2>(v, M);
+  } else {
+    if (l == 0) gate1<Real, WB, 0>(v, M);
+    if (l == 1) gate1<Real, WB, 1>(v, M);
+    if constexpr (WB >= 3)
+      if (l == 2) gate1<Real, WB, 2>(v, M);
+    if constexpr (WB >= 4)
+      if (l == 3) gate1<Real, WB, 3>(v, M);
+  }
+}
+
+template <typename Real, int WB>
+__global__ void __launch_bounds__(BW_T) bw_pass_kernel(BwPassArgs a) {
+  using C = cpx<Real>;
+  extern __shared__ char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int tid = threadIdx.x;
+  const int N = 1 << a.n;
+  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const TileMap tm = make_tile_map(tile, a.n, a.c, a.p);
+  const C* __restrict__ xin = static_cast<const C*>(a.xin);
+  C* __restrict__ xout = static_cast<C*>(a.xout);
+  for (int j = tid; j < N; j += BW_T) lds[bw_phys(j)] = xin[tm.g(j)];
+  __syncthreads();
+  const int ngroups = N >> WB;
+  for (int wi = 0; wi < a.nwin; ++wi) {
+    const BwWindow w = a.wins[wi];
+    const int b = w.b;
+    const uint32_t below = (1u << b) - 1u;
+    for (int g = tid; g < ngroups; g += BW_T) {
+      // insert WB zero bits at position b
+      const int base = static_cast<int>((uint32_t(g) & below) | ((uint32_t(g) >> b) << (b + WB)));
+      C v[1 << WB];
+#pragma unroll
+      for (int m = 0; m < (1 << WB); ++m) v[m] = lds[bw_phys(base + (m << b))];
+      for (int q = 0; q < w.ngates; ++q) apply_gate<Real, WB>(v, w.kind[q], w.l[q], a.mats + 16 * w.mat[q]);
+#pragma unroll
+      for (int m = 0; m < (1 << WB); ++m) lds[bw_phys(base + (m << b))] = v[m];
+    }
+    __syncthreads();
+  }
+  const C rot = mk<Real>(static_cast<Real>(a.rot_re), static_cast<Real>(a.rot_im));
+  const C pc = mk<Real>(static_cast<Real>(a.psi_coef_re), static_cast<Real>(a.psi_coef_im));
+  const C* __restrict__ psi = static_cast<const C*>(a.psi);
+  for (int j = tid; j < N; j += BW_T) {
+    const uint32_t g = tm.g(j);
+    C x = lds[bw_phys(j)];
+    if (a.flags & BW_ROT) x = cmul(x, rot);
+    if (a.flags & BW_ADD_PSI) x = (a.flags & BW_PSI_COEF) ? cfma(psi[g], pc, x) : cadd(x, psi[g]);
+    xout[g] = x;
+  }
+}
+
+template <typename Real, int WB>
+hipError_t launch_bw_t(const BwPassArgs& a, unsigned ntiles, hipStream_t s) {
+  const size_t shmem = size_t((1 << a.n) + (1 << (a.n - 4 > 0 ? a.n - 4 : 0)) + 1) * sizeof(cpx<Real>);
+  auto kern = bw_pass_kernel<Real, WB>;
+  if (shmem > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem));
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, dim3(ntiles), dim3(BW_T), shmem, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t bw_launch_pass(const BwPassArgs& a, bool c64_dt, int wb, unsigned ntiles, hipStream_t s) {
+  if (c64_dt) {
+    if (wb == 4) return launch_bw_t<float, 4>(a, ntiles, s);
+    if (wb == 3) return launch_bw_t<float, 3>(a, ntiles, s);
+    if (wb == 2) return launch_bw_t<float, 2>(a, ntiles, s);
+  } else {
+    if (wb == 4) return launch_bw_t<double, 4>(a, ntiles, s);
+    if (wb == 3) return launch_bw_t<double, 3>(a, ntiles, s);
+    if (wb == 2) return launch_bw_t<double, 2>(a, ntiles, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Host: gate programs
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct GateRef {
+  int site;   // first site (1-based)
+  int width;  // 1 or 2
+  int mat;    // matrix index
+};
+
+// Sites of every gate in the flat order: layer b then layer a (see floquet.h).
+void layout(int L, std::vector<std::vector<int>>* lb, std::vector<std::vector<int>>* la) {
+  lb->clear();
+  la->clear();
+  if (L % 2 == 0) {
+    lb->push_back({1});
+    for (int i = 2; i <= L - 2; i += 2) lb->push_back({i, i + 1});
+    lb->push_back({L});
+    for (int i = 1; i <= L - 1; i += 2) la->push_back({i, i + 1});
+  } else {
+    lb->push_back({1});
+    for (int i = 2; i <= L - 1; i += 2) lb->push_back({i, i + 1});
+    for (int i = 1; i <= L - 2; i += 2) la->push_back({i, i + 1});
+    la->push_back({L});
+  }
+}
+
+// Windows of up to wb consecutive tile bits covering the gates of one layer.
+// gates: (tile low bit q, width, mat)
+void pack_windows(std::vector<std::array<int, 3>> gates, int n, int wb, std::vector<BwWindow>* out) {
+  std::sort(gates.begin(), gates.end());
+  size_t i = 0;
+  while (i < gates.size()) {
+    const int q0 = gates[i][0];
+    const int b = std::max(0, std::min(q0, n - wb));
+    BwWindow w{};
+    w.b = static_cast<int8_t>(b);
+    w.ngates = 0;
+    while (i < gates.size() && gates[i][0] + gates[i][1] <= b + wb && w.ngates < 4) {
+      w.kind[w.ngates] = static_cast<int8_t>(gates[i][1]);
+      w.l[w.ngates] = static_cast<int8_t>(gates[i][0] - b);
+      w.mat[w.ngates] = static_cast<int16_t>(gates[i][2]);
+      ++w.ngates;
+      ++i;
+    }
+    out->push_back(w);
+  }
+}
+
+}  // namespace
+
+struct BwProgram {
+  // per pass: windows on the device, tile geometry
+  struct Pass {
+    int n, c, p, wb;
+    unsigned ntiles;
+    BwWindow* wins = nullptr;
+    int nwin = 0;
+  };
+  int npass = 0;
+  Pass pass[2];  // [0] applied first (right block), [1] second (left block)
+  c128* mats = nullptr;
+  bool c64 = true;
+
+  ~BwProgram() {
+    for (Pass& p : pass) (void)hipFree(p.wins);
+    (void)hipFree(mats);
+  }
+};
+
+namespace {
+
+fq_status build_program(floquet_op* op, bool c64_dt, std::shared_ptr<BwProgram>* out) {
+  const int L = op->L;
+  auto prog = std::make_shared<BwProgram>();
+  prog->c64 = c64_dt;
+  std::vector<std::vector<int>> lb, la;
+  layout(L, &lb, &la);
+  // matrices: each padded to 16 complex (one-site gates use the first 4)
+  std::vector<c128> mats;
+  std::vector<GateRef> refs_b, refs_a;
+  size_t pos = 0;
+  int mi = 0;
+  for (int layer = 0; layer < 2; ++layer) {
+    const auto& lst = layer == 0 ? lb : la;
+    for (const auto& sites : lst) {
+      const int w = static_cast<int>(sites.size());
+      const int nn = w == 1 ? 4 : 16;
+      for (int e = 0; e < 16; ++e) {
+        const zd z = e < nn ? op->gates[pos + e] : zd(0, 0);
+        mats.push_back(mk<double>(z.real(), z.imag()));
+      }
+      pos += nn;
+      (layer == 0 ? refs_b : refs_a).push_back({sites[0], w, mi++});
+    }
+  }
+  FQ_HIP_CHECK(hipMalloc(&prog->mats, mats.size() * sizeof(c128)));
+  FQ_HIP_CHECK(hipMemcpy(prog->mats, mats.data(), mats.size() * sizeof(c128), hipMemcpyHostToDevice));
+
+  const int nmax = c64_dt ? 13 : 12;
+  auto tile_bit_lo = [&](int site) { return L - site; };  // right/single pass: identity
+  if (L <= nmax) {
+    prog->npass = 1;
+    BwProgram::Pass& ps = prog->pass[0];
+    ps.n = L;
+    ps.c = L;
+    ps.p = L;
+    ps.wb = std::min(4, L);
+    ps.ntiles = 1;
+    std::vector<BwWindow> wins;
+    for (int layer = 0; layer < 2; ++layer) {
+      std::vector<std::array<int, 3>> g;
+      for (const GateRef& r : layer == 0 ? refs_b : refs_a)
+        g.push_back({tile_bit_lo(r.site + r.width - 1), r.width, r.mat});
+      pack_windows(g, ps.n, ps.wb, &wins);
+    }
+    ps.nwin = static_cast<int>(wins.size());
+    FQ_HIP_CHECK(hipMalloc(&ps.wins, wins.size() * sizeof(BwWindow)));
+    FQ_HIP_CHECK(hipMemcpy(ps.wins, wins.data(), wins.size() * sizeof(BwWindow), hipMemcpyHostToDevice));
+  } else {
+    // choose the even cut site c_s and chunk c so both tiles fit in LDS
+    // (<= 14 bits complex64, <= 13 bits complex128), balancing the two tiles
+    const int nfit = c64_dt ? 14 : 13;
+    int best_cs = -1, best_c = 0;
+    for (int c = c64_dt ? 3 : 2; c >= 1 && best_cs < 0; --c) {
+      int best_span = 1 << 30;
+      for (int cs = 4; cs <= L - 3; cs += 2) {
+        const int nR = L - cs + 1, nL = cs + c;
+        if (nR <= nfit && nL <= nfit && std::max(nR, nL) < best_span) {
+          best_span = std::max(nR, nL);
+          best_cs = cs;
+        }
+      }
+      if (best_cs >= 0) best_c = c;
+    }
+    if (best_cs < 0) {
+      set_error("brickwork: no two-tile split for L = " + std::to_string(L));
+      return FQ_EINVAL;
+    }
+    const int cs = best_cs, c = best_c;
+    prog->npass = 2;
+    // right block: sites cs..L -> global bits [0, L-cs]
+    BwProgram::Pass& pr = prog->pass[0];
+    pr.n = L - cs + 1;
+    pr.c = pr.n;
+    pr.p = pr.n;
+    pr.wb = 4;
+    pr.ntiles = 1u << (L - pr.n);
+    // left block: sites 1..cs -> global bits [L-cs, L); tile bit = c + (gbit - (L-cs))
+    BwProgram::Pass& pl = prog->pass[1];
+    pl.n = cs + c;
+    pl.c = c;
+    pl.p = L - cs;
+    pl.wb = 4;
+    pl.ntiles = 1u << (L - pl.n);
+    for (int which = 0; which < 2; ++which) {
+      BwProgram::Pass& ps = prog->pass[which];
+      std::vector<BwWindow> wins;
+      for (int layer = 0; layer < 2; ++layer) {
+        std::vector<std::array<int, 3>> g;
+        for (const GateRef& r : layer == 0 ? refs_b : refs_a) {
+          const int first = r.site, last = r.site + r.width - 1;
+          // right block: U_b's gates starting at c_s or later, U_a's gates
+          // starting right of c_s; everything else is in the left block
+          const bool right = layer == 0 ? first >= cs : first > cs;
+          const bool mine = which == 0 ? right : !right;
+          if (!mine) continue;
+          const int gbit_lo = L - last;  // global bit of the gate's last (low) site
+          const int tbit = which == 0 ? gbit_lo : c + (gbit_lo - pl.p);
+          g.push_back({tbit, r.width, r.mat});
+        }
+        if (!g.empty()) {
+          if (which == 1)
+            for (auto& e : g)
+              if (e[0] < c) {
+                set_error("internal: brickwork gate in the chunk bits");
+                return FQ_EINVAL;
+              }
+          pack_windows(g, ps.n, ps.wb, &wins);
+        }
+      }
+      ps.nwin = static_cast<int>(wins.size());
+      FQ_HIP_CHECK(hipMalloc(&ps.wins, std::max<size_t>(1, wins.size()) * sizeof(BwWindow)));
+      if (!wins.empty())
+        FQ_HIP_CHECK(hipMemcpy(ps.wins, wins.data(), wins.size() * sizeof(BwWindow), hipMemcpyHostToDevice));
+    }
+  }
+  *out = prog;
+  return FQ_OK;
+}
+
+fq_status run_pass(const BwProgram& prog, int which, const void* in, void* out, const void* psi, int flags,
+                   zd rot, zd psi_coef, hipStream_t s) {
+  const BwProgram::Pass& ps = prog.pass[which];
+  BwPassArgs a{};
+  a.xin = in;
+  a.xout = out;
+  a.psi = psi;
+  a.mats = prog.mats;
+  a.wins = ps.wins;
+  a.nwin = ps.nwin;
+  a.n = ps.n;
+  a.c = ps.c;
+  a.p = ps.p;
+  a.flags = flags;
+  a.rot_re = rot.real();
+  a.rot_im = rot.imag();
+  a.psi_coef_re = psi_coef.real();
+  a.psi_coef_im = psi_coef.imag();
+  hipError_t e = bw_launch_pass(a, prog.c64, ps.wb, ps.ntiles, s);
+  if (e != hipSuccess) {
+    set_error(std::string("brickwork pass launch failed: ") + hipGetErrorString(e));
+    return FQ_EDEVICE;
+  }
+  return FQ_OK;
+}
+
+}  // namespace
+
+fq_status bw_create(floquet_op* op) {
+  fq_status st = build_program(op, true, &op->bw32);
+  if (st != FQ_OK) return st;
+  return build_program(op, false, &op->bw64);
+}
+
+void bw_destroy(floquet_op* op) {
+  op->bw32.reset();
+  op->bw64.reset();
+}
+
+fq_status bw_apply_U(floquet_op* op, fq_dtype dt, const void* psi, void* out, hipStream_t s) {
+  const BwProgram& prog = dt == FQ_C64 ? *op->bw32 : *op->bw64;
+  const void* in = psi;
+  for (int i = 0; i < prog.npass; ++i) {
+    fq_status st = run_pass(prog, i, in, out, nullptr, 0, zd(1, 0), zd(1, 0), s);
+    if (st != FQ_OK) return st;
+    in = out;
+  }
+  return FQ_OK;
+}
+
+// Horner: w = a_k psi; k times w <- a psi + rot * U w (rot = e^{-i phi} for
+// the geometric sum, 1 for a general polynomial).
+fq_status bw_filter(floquet_op* op, int k, double phi, const zd* coefs, fq_dtype dt, const void* psi, void* out,
+                    hipStream_t s) {
+  const BwProgram& prog = dt == FQ_C64 ? *op->bw32 : *op->bw64;
+  const zd rot = coefs ? zd(1, 0) : std::polar(1.0, -phi);
+  const zd a_k = coefs ? coefs[k] : zd(1, 0);
+  if (a_k != zd(1, 0)) {
+    fq_status st = poly_scale_copy(op, a_k, dt, psi, out, s);
+    if (st != FQ_OK) return st;
+  }
+  for (int step = 1; step <= k; ++step) {
+    const void* in = (step == 1 && a_k == zd(1, 0)) ? psi : out;
+    const zd c = coefs ? coefs[k - step] : zd(1, 0);
+    const int last_flags = BW_ROT | BW_ADD_PSI | (c != zd(1, 0) ? BW_PSI_COEF : 0);
+    for (int i = 0; i < prog.npass; ++i) {
+      const bool last = i == prog.npass - 1;
+      fq_status st = run_pass(prog, i, i == 0 ? in : out, out, psi, last ? last_flags : 0, rot, c, s);
+      if (st != FQ_OK) return st;
+    }
+  }
+  return FQ_OK;
 }
 
 }  // namespace fq
