@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -127,6 +128,9 @@ void tile_shape(int n, int* rb, int* tb) {
   *tb = n - *rb;
 }
 
+// Register bits go to layout A (q >= TB) or B (q < RB); every other tile
+// bit is a lane bit of layout B (lane q - RB), where the low lane indices
+// are exchanged with DPP row permutes.
 KickMasks masks_for(unsigned kbits, int n, int rb, int tb) {
   KickMasks k{0, 0, 0, 0};
   for (int q = 0; q < n; ++q) {
@@ -135,12 +139,25 @@ KickMasks masks_for(unsigned kbits, int n, int rb, int tb) {
       k.regB |= 1u << q;
     else if (q >= tb)
       k.regA |= 1u << (q - tb);
-    else if (q < 6)
-      k.laneA |= 1u << q;
+    else if (tb <= 6 && rb == 0)
+      k.laneA |= 1u << q;  // one layout only (no register bits)
     else
       k.laneB |= 1u << (q - rb);
   }
   return k;
+}
+
+// Single-workgroup kernel: as many waves as the reachability rule allows.
+void single_shape(int L, int* rb, int* tb) {
+  if (L <= 6) {
+    *tb = 6;
+    *rb = 0;
+    return;
+  }
+  int t = std::min(8, (L + 6) / 2);
+  if (L >= 13) t = L - 4;  // 16 amplitudes per thread above 2^12
+  *tb = t;
+  *rb = L - t;
 }
 
 KiPlan make_plan(int L, bool c64_dt) {
@@ -218,7 +235,7 @@ template <typename Real>
 fq_status ki_single(floquet_op* op, const PhaseTables* tab, const void* psi, const void* xin, void* out, int steps,
                     int flags, const double2* coefs, zd in_coef, unsigned nblocks, size_t stride, hipStream_t s) {
   int rb, tb;
-  tile_shape(op->L, &rb, &tb);
+  single_shape(op->L, &rb, &tb);
   KiSingleArgs<Real> a{};
   a.xin = static_cast<const cpx<Real>*>(xin);
   a.xout = static_cast<cpx<Real>*>(out);

@@ -47,6 +47,43 @@ __device__ __forceinline__ void kick_regs(cpx<Real> (&v)[1 << RB], unsigned mask
   }
 }
 
+// Value of lane (lane ^ 2^LB) without going through LDS: DPP row permutes
+// for lane bits 0..3 (quad_perm xor 1, xor 2; half-row mirror then xor 3
+// for xor 4; row rotate by 8 for xor 8) and the gfx950 permlane swaps for
+// lane bits 4 and 5 (each output register holds the even / odd half of every
+// lane pair; the lane picks its partner's).
+__device__ __forceinline__ unsigned lane_xor_u32(unsigned u, int lb) {
+  const int x = static_cast<int>(u);
+  switch (lb) {
+    case 0:
+      return static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false));
+    case 1:
+      return static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false));
+    case 2: {
+      const int y = __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false);
+      return static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, y, 0x1B, 0xF, 0xF, false));
+    }
+    case 3:
+      return static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false));
+    case 4: {
+      const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+      return (threadIdx.x & 16u) ? r[0] : r[1];
+    }
+    default: {
+      const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+      return (threadIdx.x & 32u) ? r[0] : r[1];
+    }
+  }
+}
+
+__device__ __forceinline__ float lane_xor(float v, int lb) { return __uint_as_float(lane_xor_u32(__float_as_uint(v), lb)); }
+__device__ __forceinline__ double lane_xor(double v, int lb) {
+  const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+  const unsigned lo = lane_xor_u32(static_cast<unsigned>(b), lb);
+  const unsigned hi = lane_xor_u32(static_cast<unsigned>(b >> 32), lb);
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
 // mask: lane bits (0..5) to butterfly across the wavefront.
 template <typename Real, int RB, bool SW>
 __device__ __forceinline__ void kick_lanes(cpx<Real> (&v)[1 << RB], unsigned mask, Real w) {
@@ -55,7 +92,9 @@ __device__ __forceinline__ void kick_lanes(cpx<Real> (&v)[1 << RB], unsigned mas
     if (mask & (1u << l)) {
 #pragma unroll
       for (int m = 0; m < (1 << RB); ++m) {
-        const cpx<Real> p = shfl_xor_c(v[m], 1 << l);
+        cpx<Real> p;
+        p.x = lane_xor(v[m].x, l);
+        p.y = lane_xor(v[m].y, l);
         if constexpr (SW)
           v[m] = xpiwy(p, w, v[m]);
         else
@@ -291,7 +330,7 @@ hipError_t launch_single_t(const KiSingleArgs<Real>& a, unsigned nblocks, bool p
 
 }  // namespace
 
-#define FQ_SHAPES(X) X(0, 6) X(1, 6) X(2, 6) X(3, 6) X(4, 6) X(4, 7) X(4, 8) X(4, 9)
+#define FQ_SHAPES(X) X(0, 6) X(1, 6) X(2, 6) X(3, 6) X(4, 6) X(4, 7) X(4, 8) X(4, 9) X(1, 7) X(2, 7) X(2, 8) X(3, 8)
 
 template <typename Real>
 hipError_t ki_launch_pass(const KiPassArgs<Real>& a, int rb, int tb, bool sw, unsigned ntiles, hipStream_t s) {
