@@ -128,6 +128,16 @@ void tile_shape(int n, int* rb, int* tb) {
   *tb = n - *rb;
 }
 
+// Multi-pass tiles: few tiles per CU (small states) favour more waves per
+// tile (8 amplitudes per thread, up to 512 threads).
+void pass_shape(int n, unsigned ntiles, int* rb, int* tb) {
+  tile_shape(n, rb, tb);
+  if (ntiles <= 512 && n >= 10 && n <= 12) {
+    *rb = 3;
+    *tb = n - 3;
+  }
+}
+
 // Register bits go to layout A (q >= TB) or B (q < RB); every other tile
 // bit is a lane bit of layout B (lane q - RB), where the low lane indices
 // are exchanged with DPP row permutes.
@@ -209,7 +219,7 @@ KiPlan make_plan(int L, bool c64_dt) {
     g2.kbits = ((1u << g2.n) - 1u) & ~((1u << c) - 1u);
     g2.ntiles = 1u << (L - g2.n);
   }
-  for (int i = 0; i < pl.ngroups; ++i) tile_shape(pl.grp[i].n, &pl.grp[i].rb, &pl.grp[i].tb);
+  for (int i = 0; i < pl.ngroups; ++i) pass_shape(pl.grp[i].n, pl.grp[i].ntiles, &pl.grp[i].rb, &pl.grp[i].tb);
   return pl;
 }
 
@@ -290,6 +300,9 @@ fq_status ki_pass(floquet_op* op, const KiGroup& gp, const PhaseTables* tab, con
   a.flags = flags;
   if (in_coef != zd(1.0, 0.0)) a.flags |= KI_SCALE_IN;
   if ((flags & KI_ADD_PSI) && psi_coef != zd(1.0, 0.0)) a.flags |= KI_PSI_COEF;
+  // few tiles per CU (latency-bound): fetch the phase entries with the tile;
+  // complex128 only for the smallest states (register budget)
+  if (gp.ntiles <= (sizeof(Real) == 4 ? 1024u : 512u)) a.flags |= KI_PREFETCH_PHASE;
   a.k1 = masks_for(gp.kbits, gp.n, gp.rb, gp.tb);
   a.k2 = k2 ? a.k1 : KickMasks{0, 0, 0, 0};
   hipError_t e = ki_launch_pass<Real>(a, gp.rb, gp.tb, op->sw, gp.ntiles, s);

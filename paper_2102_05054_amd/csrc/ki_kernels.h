@@ -10,6 +10,7 @@ enum : int {
   KI_ADD_PSI = 2,    // add psi (times psi_coef if KI_PSI_COEF)
   KI_PSI_COEF = 4,
   KI_SCALE_IN = 8,   // multiply the loaded tile by in_coef
+  KI_PREFETCH_PHASE = 16,  // load the phase-table entries with the tile
 };
 
 // Which one-qubit butterflies to apply, split by where the bit lives

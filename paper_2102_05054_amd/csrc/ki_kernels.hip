@@ -115,7 +115,7 @@ __device__ __forceinline__ cpx<Real> ki_phase(const cpx<Real>* __restrict__ tlo,
 // ---------------------------------------------------------------------------
 // One pass over all tiles of one group (see ki_kernels.h for the fields).
 // ---------------------------------------------------------------------------
-template <typename Real, int RB, int TB, bool SW>
+template <typename Real, int RB, int TB, bool SW, bool PF>
 __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
   using C = cpx<Real>;
   constexpr int R = 1 << RB;
@@ -131,12 +131,23 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
   // The tile and psi are read in layout A (consecutive lanes <-> consecutive
   // addresses) at the start; the phase and +psi are applied in layout A too,
   // so every global access of the pass is coalesced.
-  C v[R], ps[R];
+  C v[R], ps[R], tl[PF ? R : 1], th[PF ? R : 1];
 #pragma unroll
   for (int m = 0; m < R; ++m) v[m] = a.xin[tm.g(tid + (m << TB))];
   if (do_ps) {
 #pragma unroll
     for (int m = 0; m < R; ++m) ps[m] = a.psi[tm.g(tid + (m << TB))];
+  }
+  // with few tiles per CU (small states) the pass is latency-bound: fetch the
+  // phase-table entries together with the tile instead of mid-pass
+  constexpr bool pre_ph = PF;
+  if constexpr (PF) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const uint32_t g = tm.g(tid + (m << TB));
+      tl[m] = a.tlo[g & ((1u << a.m) - 1u)];
+      th[m] = a.thi[((g >> a.m) << 2) | ((g & 1u) << 1) | ((g >> (a.m - 1)) & 1u)];
+    }
   }
   if (a.flags & KI_SCALE_IN) {
     const C s = mk<Real>(static_cast<Real>(a.in_coef_re), static_cast<Real>(a.in_coef_im));
@@ -161,7 +172,11 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
 #pragma unroll
     for (int m = 0; m < R; ++m) {
       C x = v[m];
-      if (do_ph) x = cmul(x, ki_phase(a.tlo, a.thi, tm.g(tid + (m << TB)), a.m));
+      if constexpr (pre_ph) {
+        if (do_ph) x = cmul(x, cmul(tl[m], th[m]));
+      } else {
+        if (do_ph) x = cmul(x, ki_phase(a.tlo, a.thi, tm.g(tid + (m << TB)), a.m));
+      }
       if (do_ps) x = coef ? cfma(ps[m], pc, x) : cadd(x, ps[m]);
       v[m] = x;
     }
@@ -286,10 +301,10 @@ __global__ void cast_c64_to_c128(const c64* __restrict__ in, c128* __restrict__ 
 // ---------------------------------------------------------------------------
 namespace {
 
-template <typename Real, int RB, int TB, bool SW>
+template <typename Real, int RB, int TB, bool SW, bool PF>
 hipError_t launch_pass_t(const KiPassArgs<Real>& a, unsigned ntiles, hipStream_t s) {
   const size_t shmem = static_cast<size_t>(lds_slots<RB, TB>()) * sizeof(cpx<Real>);
-  auto kern = ki_pass_kernel<Real, RB, TB, SW>;
+  auto kern = ki_pass_kernel<Real, RB, TB, SW, PF>;
   static bool attr_set = false;
   if (!attr_set && shmem > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -330,14 +345,19 @@ hipError_t launch_single_t(const KiSingleArgs<Real>& a, unsigned nblocks, bool p
 
 }  // namespace
 
-#define FQ_SHAPES(X) X(0, 6) X(1, 6) X(2, 6) X(3, 6) X(4, 6) X(4, 7) X(4, 8) X(4, 9) X(1, 7) X(2, 7) X(2, 8) X(3, 8)
+#define FQ_SHAPES(X) X(0, 6) X(1, 6) X(2, 6) X(3, 6) X(4, 6) X(4, 7) X(4, 8) X(4, 9) X(1, 7) X(2, 7) X(2, 8) X(3, 8) X(3, 7) X(3, 9)
 
 template <typename Real>
 hipError_t ki_launch_pass(const KiPassArgs<Real>& a, int rb, int tb, bool sw, unsigned ntiles, hipStream_t s) {
-#define FQ_CASE(RB_, TB_)                                                  \
-  if (rb == RB_ && tb == TB_)                                              \
-    return sw ? launch_pass_t<Real, RB_, TB_, true>(a, ntiles, s)          \
-              : launch_pass_t<Real, RB_, TB_, false>(a, ntiles, s);
+  const bool pf = (a.flags & KI_PREFETCH_PHASE) != 0;
+#define FQ_CASE(RB_, TB_)                                                                          \
+  if (rb == RB_ && tb == TB_) {                                                                    \
+    if (pf)                                                                                        \
+      return sw ? launch_pass_t<Real, RB_, TB_, true, true>(a, ntiles, s)                          \
+                : launch_pass_t<Real, RB_, TB_, false, true>(a, ntiles, s);                        \
+    return sw ? launch_pass_t<Real, RB_, TB_, true, false>(a, ntiles, s)                           \
+              : launch_pass_t<Real, RB_, TB_, false, false>(a, ntiles, s);                         \
+  }
   FQ_SHAPES(FQ_CASE)
 #undef FQ_CASE
   return hipErrorInvalidValue;
