@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-c128", action="store_true", help="skip the complex128 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--roofline-steps", type=int, default=2000)
+    ap.add_argument("--profile-filter", action="store_true",
+                    help="only the complex64 Horner filter (k=200) and a 64 MiB device copy, for counter runs")
     return ap.parse_args()
 
 
@@ -76,6 +78,43 @@ def filter_roofline(op, L, steps):
         "achieved_GBs": bytes_per_launch / avg_s / 1e9,
         "U_apps_per_s": 1.0 / avg_s,
     }
+
+
+COPY_BYTES = 2 ** 30
+
+
+def profile_filter(op, L):
+    """Workload of the counter runs: 200 Horner passes (complex64) and one plain
+    device-to-device copy of COPY_BYTES (1 GiB, source evicted from L2 and the
+    Infinity Cache by a second 1 GiB write) that calibrates FETCH_SIZE /
+    WRITE_SIZE in bytes."""
+    import torch
+    psi = torch.randn(2 ** L, dtype=torch.complex64, device="cuda")
+    out = torch.empty_like(psi)
+    op.apply_filter(psi, 200, 0.0, out=out)
+    a = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda").fill_(1)
+    c = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda").fill_(2)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    # second calibration copy through torch's elementwise kernel (float32 view)
+    torch.mul(c.view(torch.float32), 1.0, out=a.view(torch.float32))
+    torch.cuda.synchronize()
+    del c
+    print(json.dumps({"profile_filter": True, "L": L, "copy_bytes": COPY_BYTES}))
+
+
+def traffic_per_pass():
+    """Calibrated HBM bytes per pass from the committed counter summary, only
+    when it was measured on the current kernel source."""
+    try:
+        from paper_2102_05054_amd.traffic import kernel_hash
+        with open(os.path.join(ROOT, "profiles", "ki_pass_kernel_L20_traffic.json")) as f:
+            rec = json.load(f)
+        if rec.get("kernel_hash") == kernel_hash():
+            return rec["bytes_per_pass"]
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
 
 
 def cpu_baseline(p, seconds=15.0):
@@ -121,6 +160,11 @@ def main():
     p = config_kicked_ising("ki_L20", W=args.W, L=L)
     op = kicked_ising(p.L, p.J, p.h, p.g, p.periodic)
     d = 2 ** L
+
+    if args.profile_filter:
+        profile_filter(op, L)
+        op.close()
+        return
 
     def solve(dtype):
         torch.cuda.synchronize()
@@ -186,7 +230,7 @@ def main():
             "peak": 8000.0,
             "unit": "GB/s",
             "frac": roof["achieved_GBs"] / 8000.0,
-            "traffic": None,
+            "traffic": traffic_per_pass(),
             "kernel": roof["kernel"],
             "avg_launch_us": roof["avg_launch_us"],
             "bytes_per_launch": roof["bytes_per_launch"],

@@ -1,0 +1,89 @@
+"""HBM traffic of the Horner pass kernel from rocprofv3 counter runs.
+
+rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) over ``bench.py --profile-filter``
+reports KiB per dispatch for the pass kernels and for a plain device copy of
+known size (the calibration: the copy moves exactly ``copy_bytes`` each way).
+``summarise`` turns the two counter CSVs into bytes per pass launch, scaled by
+the copy's known / measured ratio, and records the hash of the kernel source so
+that a stale measurement is never reported for a changed kernel.
+
+Usage:
+  python -m paper_2102_05054_amd.traffic FETCH.csv WRITE.csv COPY_BYTES OUT.json
+"""
+
+from __future__ import annotations
+
+import csv
+import hashlib
+import json
+import os
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ["csrc/ki_kernels.hip", "csrc/tile_engine.h", "csrc/ki_kernels.h"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _per_kernel(path):
+    acc = defaultdict(list)
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}, {k: len(v) for k, v in acc.items()}
+
+
+def summarise(fetch_csv, write_csv, copy_bytes):
+    fetch, nf = _per_kernel(fetch_csv)
+    write, _ = _per_kernel(write_csv)
+    copy_names = [k for k in fetch if ("copyBuffer" in k or "elementwise" in k or "vectorized" in k)
+                  and "ki_pass" not in k and fetch[k] * 1024.0 > 0.05 * copy_bytes]
+    if not copy_names:
+        raise RuntimeError("no copy kernel in the counter runs")
+    for k in copy_names:
+        print(f"calibration {k[:70]}: fetch factor {copy_bytes / (fetch[k] * 1024.0):.3f}, "
+              f"write factor {copy_bytes / (write[k] * 1024.0):.3f}", file=sys.stderr)
+    # the plain elementwise copy uses the same global load/store instructions as
+    # the pass kernel; the runtime's blit kernel reads differently and is only
+    # reported
+    plain = [k for k in copy_names if "elementwise" in k or "vectorized" in k]
+    cname = plain[0] if plain else copy_names[0]
+    factors = {k: {"fetch": copy_bytes / (fetch[k] * 1024.0), "write": copy_bytes / (write[k] * 1024.0)}
+               for k in copy_names}
+    f_factor = copy_bytes / (fetch[cname] * 1024.0)
+    w_factor = copy_bytes / (write[cname] * 1024.0)
+    passes = {}
+    for k in fetch:
+        if "ki_pass_kernel<float" in k:
+            passes[k] = {
+                "fetch_bytes": fetch[k] * 1024.0 * f_factor,
+                "write_bytes": write.get(k, 0.0) * 1024.0 * w_factor,
+                "dispatches": nf[k],
+            }
+    tot_f = sum(v["fetch_bytes"] * v["dispatches"] for v in passes.values())
+    tot_w = sum(v["write_bytes"] * v["dispatches"] for v in passes.values())
+    n = sum(v["dispatches"] for v in passes.values())
+    return {
+        "kernel_hash": kernel_hash(),
+        "copy_kernel": cname,
+        "calibration_factors": factors,
+        "copy_bytes": copy_bytes,
+        "fetch_factor": f_factor,
+        "write_factor": w_factor,
+        "per_kernel": passes,
+        "bytes_per_pass": (tot_f + tot_w) / max(n, 1),
+    }
+
+
+if __name__ == "__main__":
+    out = summarise(sys.argv[1], sys.argv[2], float(sys.argv[3]))
+    with open(sys.argv[4], "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
