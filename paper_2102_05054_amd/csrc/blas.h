@@ -42,7 +42,8 @@ hipError_t launch_scale_c64(const c64* in, double are, double aim, c64* out, siz
 // y = y - a * x   (a on the device, complex)
 hipError_t launch_axpy_dev(const c128* a, const c128* x, c128* y, size_t d, hipStream_t s);
 // Y[:, c] = sum_{i<m} V[:, i] Q[i, c] for c < p.  Y may equal V (in place, p <= m).
-// Q: m x p complex128 column-major (ldq = m) on the device.
+// Q: m x p complex128, k-major (Q[i*p + c]) on the device.  FP64 matrix cores
+// for p <= 256 and d a multiple of 16.
 hipError_t launch_basis_gemm(const c128* V, size_t ldv, int m, const c128* Q, int p, c128* Y, size_t ldy,
                              size_t d, hipStream_t s);
 // v[i] = counter-based uniform complex in [-1, 1)^2 from (seed, i)

@@ -271,7 +271,7 @@ __global__ void axpy_dev_kernel(const c128* __restrict__ a, const c128* __restri
 
 // Y[r, c] = sum_i V[r, i] Q[i, c] for a block of BR rows staged in LDS
 // (transposed, lds[i*BR + r]); all of a block's rows are read before any is
-// written, so Y may alias V.
+// written, so Y may alias V.  Q is k-major: Q[i*p + c].  Fallback for p > 256.
 __global__ void __launch_bounds__(NT) basis_gemm_kernel(const c128* __restrict__ V, size_t ldv, int m,
                                                         const c128* __restrict__ Q, int p, c128* Y, size_t ldy,
                                                         size_t d, int BR) {
@@ -286,16 +286,69 @@ __global__ void __launch_bounds__(NT) basis_gemm_kernel(const c128* __restrict__
   __syncthreads();
   for (int o = tid; o < BR * p; o += NT) {
     const int r = o % BR, c = o / BR;
-    const c128* q = Q + size_t(c) * m;
     double sx = 0.0, sy = 0.0;
     for (int i = 0; i < m; ++i) {
       const c128 a = st[i * BR + r];
-      const c128 b = q[i];
+      const c128 b = Q[size_t(i) * p + c];
       sx += a.x * b.x - a.y * b.y;
       sy += a.x * b.y + a.y * b.x;
     }
     const size_t row = r0 + r;
     if (row < d) Y[size_t(c) * ldy + row] = mk<double>(sx, sy);
+  }
+}
+
+// The same product on the FP64 matrix cores (v_mfma_f64_16x16x4f64).  One
+// wavefront owns 16 rows and all p <= 256 columns, streaming V's 16-row
+// slices over k in steps of 4 and keeping the 16x16 output tiles of the real
+// and imaginary parts in accumulators; rows are written only after the last
+// k, so Y may alias V.  Complex product with four real MFMAs per tile:
+//   Re += Vr Qr + (-Vi) Qi,   Im += Vr Qi + Vi Qr.
+// Operand layout: A lane l = A[l%16][l/16], B lane l = B[l/16][l%16],
+// D lane l register r = D[4r + l/16][l%16].
+typedef double fq_d4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(64) basis_gemm_mfma_kernel(const c128* __restrict__ V, size_t ldv, int m,
+                                                             const c128* __restrict__ Q, int p, c128* Y, size_t ldy) {
+  constexpr int MAXT = 16;
+  const int l = threadIdx.x;
+  const size_t r0 = static_cast<size_t>(blockIdx.x) * 16;
+  const int ntile = (p + 15) >> 4;
+  fq_d4 accr[MAXT], acci[MAXT];
+#pragma unroll
+  for (int t = 0; t < MAXT; ++t) {
+    accr[t] = fq_d4{0.0, 0.0, 0.0, 0.0};
+    acci[t] = fq_d4{0.0, 0.0, 0.0, 0.0};
+  }
+  const int lr = l & 15, lk = l >> 4;
+  for (int k0 = 0; k0 < m; k0 += 4) {
+    const int k = k0 + lk;
+    const c128 a = k < m ? V[size_t(k) * ldv + r0 + lr] : mk<double>(0, 0);
+    const double nai = -a.y;
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t) {
+      if (t < ntile) {
+        const int col = (t << 4) + lr;
+        const c128 b = (k < m && col < p) ? Q[size_t(k) * p + col] : mk<double>(0, 0);
+        accr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, accr[t], 0, 0, 0);
+        accr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, b.y, accr[t], 0, 0, 0);
+        acci[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, acci[t], 0, 0, 0);
+        acci[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, acci[t], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < MAXT; ++t) {
+    if (t < ntile) {
+      const int col = (t << 4) + lr;
+      if (col < p) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 4 * r + lk;
+          Y[size_t(col) * ldy + r0 + i] = mk<double>(accr[t][r], acci[t][r]);
+        }
+      }
+    }
   }
 }
 
@@ -386,6 +439,11 @@ hipError_t launch_axpy_dev(const c128* a, const c128* x, c128* y, size_t d, hipS
 
 hipError_t launch_basis_gemm(const c128* V, size_t ldv, int m, const c128* Q, int p, c128* Y, size_t ldy, size_t d,
                              hipStream_t s) {
+  if (p <= 256 && d % 16 == 0 && d >= 16) {
+    hipLaunchKernelGGL(basis_gemm_mfma_kernel, dim3(static_cast<unsigned>(d / 16)), dim3(64), 0, s, V, ldv, m, Q, p,
+                       Y, ldy);
+    return hipGetLastError();
+  }
   int BR = 64;
   while (BR > 1 && size_t(BR) * m * sizeof(c128) > 65536) BR >>= 1;
   const size_t shmem = size_t(BR) * m * sizeof(c128);

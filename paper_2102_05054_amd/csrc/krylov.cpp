@@ -178,9 +178,9 @@ struct Ritz {
 // residual for each (Sec. 4).
 fq_status ritz_and_residuals(floquet_op* op, const Ws& ws, int m, const ZMat& X, int nev, Ritz* out,
                              hipStream_t s, long long* uapps) {
-  std::vector<c128> q(size_t(m) * nev);
+  std::vector<c128> q(size_t(m) * nev);  // k-major
   for (int c = 0; c < nev; ++c)
-    for (int i = 0; i < m; ++i) q[size_t(c) * m + i] = mk<double>(X(i, c).real(), X(i, c).imag());
+    for (int i = 0; i < m; ++i) q[size_t(i) * nev + c] = mk<double>(X(i, c).real(), X(i, c).imag());
   FQ_HIP_CHECK(hipMemcpyAsync(ws.qbuf, q.data(), q.size() * sizeof(c128), hipMemcpyHostToDevice, s));
   FQ_HIP_CHECK(launch_basis_gemm(ws.V, ws.d, m, ws.qbuf, nev, ws.ritz, ws.d, ws.d, s));
   out->omega.assign(nev, zd(0, 0));
@@ -337,9 +337,9 @@ struct Solver {
         // restart: keep p_keep Schur vectors
         const double t3 = now_s();
         const int p = p_keep;
-        std::vector<c128> q(size_t(m) * p);
+        std::vector<c128> q(size_t(m) * p);  // k-major
         for (int c = 0; c < p; ++c)
-          for (int i = 0; i < m; ++i) q[size_t(c) * m + i] = mk<double>(Z(i, c).real(), Z(i, c).imag());
+          for (int i = 0; i < m; ++i) q[size_t(i) * p + c] = mk<double>(Z(i, c).real(), Z(i, c).imag());
         FQ_HIP_CHECK(hipMemcpyAsync(ws.qbuf, q.data(), q.size() * sizeof(c128), hipMemcpyHostToDevice, s));
         FQ_HIP_CHECK(launch_basis_gemm(ws.V, ws.d, m, ws.qbuf, p, ws.V, ws.d, ws.d, s));
         FQ_HIP_CHECK(hipMemcpyAsync(ws.V + size_t(p) * ws.d, ws.V + size_t(m) * ws.d, ws.d * sizeof(c128),
