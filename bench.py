@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-c128", action="store_true", help="skip the complex128 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--roofline-steps", type=int, default=2000)
+    ap.add_argument("--scan-L", type=int, default=None,
+                    help="(n_cv, k) scan of the brickwork circuit at this L (n_ev=50, z=1, complex128)")
     ap.add_argument("--profile-filter", action="store_true",
                     help="only the complex64 Horner filter (k=200) and a 64 MiB device copy, for counter runs")
     return ap.parse_args()
@@ -117,6 +119,41 @@ def traffic_per_pass():
     return None
 
 
+def scan(L, nev=50):
+    """Runtime over a grid of (n_cv, k) for the brickwork random circuit (the
+    setting of the paper's Fig. "bench": n_ev = 50, z = 1).  Each line gives
+    time, U-applications and restarts; the rule n_cv = 0.8 * 2^(L+1) / k is
+    printed next to it."""
+    import torch
+
+    from paper_2102_05054_amd import brickwork, paper_parameters
+    from workloads import brickwork as bw_params
+    p = bw_params(L, 5000 + L)
+    op = brickwork(L, p.gates)
+    d = 2 ** L
+    ncv0, k0 = paper_parameters(L, nev)
+    ks = sorted({max(4, int(k0 * f)) for f in (0.25, 0.5, 1.0, 2.0, 4.0)})
+    ncvs = sorted({min(d - 1, max(2 * nev + 2, int(ncv0 * f))) for f in (0.5, 0.7, 1.0, 1.4, 2.0)})
+    rows = []
+    for ncv in ncvs:
+        for k in ks:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ev, _, res, st, status = op.arnoldi_eigs(nev, 0.0, k=k, ncv=ncv, tol=1e-10, max_restarts=60,
+                                                     seed=1, want_vectors=False, allow_not_converged=True)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            rows.append({"L": L, "ncv": ncv, "k": k, "time_s": dt, "U_apps": st["n_U_apps"],
+                         "restarts": st["n_restarts"], "nconv": st["nconv"], "status": int(status),
+                         "max_residual": float(res.max()), "rule_ncv_0.8": 0.8 * 2 ** (L + 1) / k,
+                         "apple_ncv": 2 ** (L + 1) / (k + 1)})
+            print(json.dumps(rows[-1]), flush=True)
+    ok = [r for r in rows if r["status"] == 0]
+    best = min(ok, key=lambda r: r["time_s"]) if ok else None
+    print(json.dumps({"scan_L": L, "paper_rule": {"ncv": ncv0, "k": k0}, "fastest": best}))
+    op.close()
+
+
 def cpu_baseline(p, seconds=15.0):
     """The oracle's matrix-free U (complex128 NumPy) on the host: U-apps/s on a
     bounded sample of the same state size."""
@@ -155,6 +192,9 @@ def main():
     from paper_2102_05054_amd import kicked_ising
     from workloads import config_kicked_ising
 
+    if args.scan_L is not None:
+        scan(args.scan_L)
+        return
     L = args.L
     k = args.k if args.k is not None else int(math.floor(0.8 * 2 ** (L + 1) / args.ncv))
     p = config_kicked_ising("ki_L20", W=args.W, L=L)

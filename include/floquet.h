@@ -171,6 +171,16 @@ fq_status arnoldi_eigs_batched(floquet_op* const* ops, int n_ops, const double* 
                                void* const* evecs_dev, double* resid_host,
                                fq_arnoldi_stats* stats, void* hip_stream);
 
+/*
+ * The paper's parameter rule for large L (Sec. 5 and the caption of Table
+ * "bench"): n_cv = floor(2^(L/2 + 1)), raised to at least 2*nev + 1 (Sec. 4:
+ * n_cv > 2 n_ev), and k = floor(0.8 * 2^(L+1) / n_cv), the Krylov dimension
+ * sitting at 80% of the eigenvalue count on the outer "apple" line of
+ * g_k (Sec. 3, last paragraph).  Host-only; returns FQ_EINVAL for L outside
+ * [2, 30] or nev < 1.
+ */
+fq_status fq_paper_parameters(int L, int nev, int* ncv_out, int* k_out);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* floquet_last_error(void);
 

@@ -65,6 +65,7 @@ SIGNATURES = [
                                      POINTER(c_double), POINTER(FqArnoldiStats), c_void_p]),
     ("floquet_last_error", ctypes.c_char_p, []),
     ("fq_host_schur", c_int, [c_int, POINTER(c_double), POINTER(c_double), POINTER(c_double)]),
+    ("fq_paper_parameters", c_int, [c_int, c_int, POINTER(c_int), POINTER(c_int)]),
 ]
 
 _lib = None

@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import (FQ_BRICKWORK, FQ_C64, FQ_C128, FQ_KICKED_ISING, FQ_NOT_CONVERGED, FQ_OK,
                    FqArnoldiOpts, FqArnoldiStats, FqModelDesc, check, lib)
 
-__all__ = ["FloquetOp", "kicked_ising", "brickwork", "arnoldi_eigs_batched", "host_schur"]
+__all__ = ["FloquetOp", "kicked_ising", "brickwork", "arnoldi_eigs_batched", "host_schur", "paper_parameters"]
 
 
 def _torch():
@@ -202,3 +202,10 @@ def host_schur(A: np.ndarray):
     T = (ab[0::2] + 1j * ab[1::2]).reshape(n, n).T
     Z = (zb[0::2] + 1j * zb[1::2]).reshape(n, n).T
     return T, Z, wb[0::2] + 1j * wb[1::2]
+
+
+def paper_parameters(L: int, nev: int):
+    """(ncv, k) from the paper's rule (see fq_paper_parameters in include/floquet.h)."""
+    ncv, k = ctypes.c_int(), ctypes.c_int()
+    check(lib().fq_paper_parameters(int(L), int(nev), ctypes.byref(ncv), ctypes.byref(k)), "fq_paper_parameters")
+    return ncv.value, k.value

@@ -594,6 +594,22 @@ fq_status arnoldi_eigs_batched(floquet_op* const* ops, int n_ops, const double* 
   return worst;
 }
 
+fq_status fq_paper_parameters(int L, int nev, int* ncv_out, int* k_out) {
+  clear_error();
+  if (L < 2 || L > 30 || nev < 1 || !ncv_out || !k_out) {
+    set_error("fq_paper_parameters: need 2 <= L <= 30, nev >= 1 and output pointers");
+    return FQ_EINVAL;
+  }
+  const double d = std::ldexp(1.0, L);
+  long long ncv = static_cast<long long>(std::floor(std::pow(2.0, L / 2.0 + 1.0)));
+  ncv = std::max<long long>(ncv, 2LL * nev + 1);
+  ncv = std::min<long long>(ncv, static_cast<long long>(d));
+  const long long k = static_cast<long long>(std::floor(0.8 * 2.0 * d / double(ncv)));
+  *ncv_out = static_cast<int>(ncv);
+  *k_out = static_cast<int>(std::max<long long>(k, 1));
+  return FQ_OK;
+}
+
 fq_status fq_host_schur(int n, double* a_host, double* z_host, double* w_host) {
   clear_error();
   if (n < 1 || !a_host || !z_host || !w_host) {

@@ -87,3 +87,16 @@ def test_host_schur_hessenberg_with_clusters():
     T, Z, w = host_schur(A)
     assert np.linalg.norm(Z @ T @ Z.conj().T - A) < 1e-12 * np.linalg.norm(A)
     assert np.all(np.diff(np.abs(w)) <= 1e-12 * 100)
+
+
+@pytest.mark.parametrize("L,nev", [(10, 50), (12, 50), (16, 50), (20, 50), (20, 100)])
+def test_paper_parameter_rule(L, nev):
+    # Table "bench" caption: n_cv = floor(2^(L/2+1)), k = 0.8 * 2^(L+1) / n_cv
+    # (k floored); n_cv > 2 n_ev (Sec. 4).  The table's L = 20 row: n_cv = 2048, k = 819.
+    from paper_2102_05054_amd import paper_parameters
+    ncv, k = paper_parameters(L, nev)
+    expect_ncv = max(int(2 ** (L / 2 + 1)), 2 * nev + 1)
+    assert ncv == expect_ncv
+    assert k == int(0.8 * 2 ** (L + 1) / ncv)
+    if L == 20 and nev == 50:
+        assert (ncv, k) == (2048, 819)
