@@ -172,6 +172,18 @@ fq_status arnoldi_eigs_batched(floquet_op* const* ops, int n_ops, const double* 
                                fq_arnoldi_stats* stats, void* hip_stream);
 
 /*
+ * Entanglement entropy S_A = -sum_i s_i^2 ln s_i^2 of n_states complex128
+ * states for the cut between sites LA and LA+1 (Sec. 5, Eq. (ee)); s_i are the
+ * singular values of the state reshaped as a 2^LA x 2^(L-LA) matrix (site 1 =
+ * most significant bit), normalised so that sum s_i^2 = 1.
+ * states_dev: n_states x d complex128, state q at offset q*d (e.g. the evecs of
+ * arnoldi_eigs).  entropy_host: n_states doubles.  Requires 1 <= LA < L and
+ * min(LA, L-LA) <= 11.  Synchronous on hip_stream.
+ */
+fq_status entanglement_entropy(const floquet_op* op, int LA, const void* states_dev, int n_states,
+                               double* entropy_host, void* hip_stream);
+
+/*
  * The paper's parameter rule for large L (Sec. 5 and the caption of Table
  * "bench"): n_cv = floor(2^(L/2 + 1)), raised to at least 2*nev + 1 (Sec. 4:
  * n_cv > 2 n_ev), and k = floor(0.8 * 2^(L+1) / n_cv), the Krylov dimension
@@ -193,6 +205,13 @@ const char* floquet_last_error(void);
  * iteration does not converge.
  */
 fq_status fq_host_schur(int n, double* a_host, double* z_host, double* w_host);
+
+/*
+ * Host-only helper exposed for testing the eigenvalue step of
+ * entanglement_entropy: ascending eigenvalues of an n x n Hermitian
+ * complex128 matrix (row-major, interleaved; overwritten).
+ */
+fq_status fq_host_eigvalsh(int n, double* a_host, double* w_host);
 
 #ifdef __cplusplus
 }

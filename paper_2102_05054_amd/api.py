@@ -147,6 +147,20 @@ class FloquetOp:
         check(st, "arnoldi_eigs", allow=(FQ_OK, FQ_NOT_CONVERGED) if allow_not_converged else (FQ_OK,))
         return evals[0::2] + 1j * evals[1::2], evecs, resid, stats.as_dict(), st
 
+    def entanglement_entropy(self, states, LA: int, stream=None):
+        """S_A for each row of ``states`` (n x d complex128 device tensor), cut after site LA."""
+        torch = _torch()
+        if states.dim() == 1:
+            states = states.unsqueeze(0)
+        if not states.is_cuda or states.dtype != torch.complex128 or not states.is_contiguous() \
+                or states.shape[1] != self.dim:
+            raise ValueError(f"states must be a contiguous complex128 device tensor of shape (n, {self.dim})")
+        out = np.zeros(states.shape[0])
+        check(lib().entanglement_entropy(self.handle, int(LA), _dptr(states), int(states.shape[0]),
+                                         out.ctypes.data_as(POINTER(c_double)), _stream_ptr(stream)),
+              "entanglement_entropy")
+        return out
+
 
 def kicked_ising(L: int, J, h, g: float, periodic: bool = True) -> FloquetOp:
     """Kicked-Ising U = D K (see include/floquet.h)."""

@@ -46,6 +46,9 @@ hipError_t launch_axpy_dev(const c128* a, const c128* x, c128* y, size_t d, hipS
 // for p <= 256 and d a multiple of 16.
 hipError_t launch_basis_gemm(const c128* V, size_t ldv, int m, const c128* Q, int p, c128* Y, size_t ldy,
                              size_t d, hipStream_t s);
+// G (n x n, row-major) = sum_t A(i,t) conj(A(j,t)), A(i,t) = X[i*si + t*st],
+// conjugated when conj_in
+hipError_t launch_gram(const c128* X, size_t si, size_t st, bool conj_in, int n, size_t T, c128* G, hipStream_t s);
 // v[i] = counter-based uniform complex in [-1, 1)^2 from (seed, i)
 hipError_t launch_random(c128* v, size_t d, unsigned long long seed, hipStream_t s);
 

@@ -352,6 +352,42 @@ __global__ void __launch_bounds__(64) basis_gemm_mfma_kernel(const c128* __restr
   }
 }
 
+// Gram matrix G[i][j] = sum_t A(i,t) conj(A(j,t)), A(i,t) = X[i*si + t*st]
+// (conjugated if cj): 16x16 output tiles, 64-long t chunks staged in LDS.
+__global__ void __launch_bounds__(256) gram_kernel(const c128* __restrict__ X, size_t si, size_t st, int cj, int n,
+                                                   size_t T, c128* __restrict__ G) {
+  __shared__ c128 As[16][65], Bs[16][65];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
+  double sx = 0.0, sy = 0.0;
+  for (size_t t0 = 0; t0 < T; t0 += 64) {
+    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+      const int r = e >> 6, c = e & 63;
+      const size_t t = t0 + c;
+      c128 a = mk<double>(0, 0), b = mk<double>(0, 0);
+      if (t < T) {
+        if (i0 + r < n) a = X[size_t(i0 + r) * si + t * st];
+        if (j0 + r < n) b = X[size_t(j0 + r) * si + t * st];
+        if (cj) {
+          a.y = -a.y;
+          b.y = -b.y;
+        }
+      }
+      As[r][c] = a;
+      Bs[r][c] = b;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int c = 0; c < 64; ++c) {
+      const c128 a = As[ty][c], b = Bs[tx][c];
+      sx += a.x * b.x + a.y * b.y;  // a * conj(b)
+      sy += a.y * b.x - a.x * b.y;
+    }
+    __syncthreads();
+  }
+  if (i0 + ty < n && j0 + tx < n) G[size_t(i0 + ty) * n + (j0 + tx)] = mk<double>(sx, sy);
+}
+
 __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
   x += 0x9E3779B97F4A7C15ull;
   x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -450,6 +486,12 @@ hipError_t launch_basis_gemm(const c128* V, size_t ldv, int m, const c128* Q, in
   if (shmem > 65536) return hipErrorInvalidValue;
   const unsigned grid = static_cast<unsigned>((d + BR - 1) / BR);
   hipLaunchKernelGGL(basis_gemm_kernel, dim3(grid), dim3(NT), shmem, s, V, ldv, m, Q, p, Y, ldy, d, BR);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram(const c128* X, size_t si, size_t st, bool conj_in, int n, size_t T, c128* G, hipStream_t s) {
+  const unsigned nb = static_cast<unsigned>((n + 15) / 16);
+  hipLaunchKernelGGL(gram_kernel, dim3(nb, nb), dim3(256), 0, s, X, si, st, conj_in ? 1 : 0, n, T, G);
   return hipGetLastError();
 }
 

@@ -100,3 +100,27 @@ def test_paper_parameter_rule(L, nev):
     assert k == int(0.8 * 2 ** (L + 1) / ncv)
     if L == 20 and nev == 50:
         assert (ncv, k) == (2048, 819)
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (5, 2), (64, 3), (300, 4)])
+def test_host_hermitian_eigenvalues_against_lapack(n, seed):
+    # the eigenvalue step of entanglement_entropy (Householder + implicit QL)
+    from paper_2102_05054_amd import _lib
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    A = X @ X.conj().T / n  # Hermitian PSD like a reduced density matrix
+    a = np.stack([A.real, A.imag], axis=-1).reshape(-1).copy()
+    w = np.zeros(n)
+    assert _lib.lib().fq_host_eigvalsh(n, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == 0
+    assert np.allclose(w, np.linalg.eigvalsh(A), atol=1e-12 * max(1.0, np.abs(A).max()) * n)
+
+
+def test_host_hermitian_eigenvalues_degenerate_and_diagonal():
+    from paper_2102_05054_amd import _lib
+    A = np.diag([0.5, 0.25, 0.25, 0.0]).astype(complex)
+    a = np.stack([A.real, A.imag], axis=-1).reshape(-1).copy()
+    w = np.zeros(4)
+    assert _lib.lib().fq_host_eigvalsh(4, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == 0
+    assert np.allclose(w, [0.0, 0.25, 0.25, 0.5], atol=1e-15)
