@@ -160,15 +160,28 @@ fq_status arnoldi_eigs(floquet_op* op, int nev, double phi, const fq_arnoldi_opt
                        fq_arnoldi_stats* stats, void* hip_stream);
 
 /*
- * Many independent problems in one call: every op in ops[0..n_ops) and every
- * target in phis[0..n_phi) (problem p = i*n_phi + j).  Ops may have different L.
+ * Many independent problems in one call (the disorder averages of Sec. 5):
+ * every op in ops[0..n_ops) and every target in phis[0..n_phi) (problem
+ * p = i*n_phi + j).  Ops may have different L and couplings.
+ * k_per_op:   n_ops filter orders (host), or NULL for opts->k everywhere; the
+ *             rule of fq_paper_parameters gives one per chain length.
  * evals_host: n_ops*n_phi*2*nev doubles; evecs_dev: n_ops*n_phi pointers (each
  * d_i x nev complex128, or NULL); resid_host: n_ops*n_phi*nev doubles or NULL;
- * stats: n_ops*n_phi entries or NULL.  Returns the worst status over problems.
+ * stats: n_ops*n_phi entries or NULL.  opts->v0_dev must be NULL (every
+ * problem starts from the seeded vector).
+ * Kicked-Ising problems (L >= 4, nev and the kept Schur vectors <= 256) of one
+ * chain length, kick form and filter order advance in lockstep: one launch
+ * per Horner pass and per CGS2 kernel for all of them, the projected
+ * matrices analysed on host threads.  Each problem runs the algorithm of
+ * arnoldi_eigs; its stats times are those of its batch.  Other problems are
+ * solved one after another.  The workspace (about d*(ncv+nev+5)*16 bytes per
+ * problem) is allocated per batch and freed before return; batches are split
+ * to fit free device memory.  Returns the worst status over problems
+ * (FQ_EINVAL also for k_per_op[i] < 1 or a non-NULL opts->v0_dev).
  */
 fq_status arnoldi_eigs_batched(floquet_op* const* ops, int n_ops, const double* phis, int n_phi,
-                               int nev, const fq_arnoldi_opts* opts, double* evals_host,
-                               void* const* evecs_dev, double* resid_host,
+                               int nev, const fq_arnoldi_opts* opts, const int* k_per_op,
+                               double* evals_host, void* const* evecs_dev, double* resid_host,
                                fq_arnoldi_stats* stats, void* hip_stream);
 
 /*

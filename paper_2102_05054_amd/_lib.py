@@ -61,8 +61,8 @@ SIGNATURES = [
     ("arnoldi_eigs", c_int, [c_void_p, c_int, c_double, POINTER(FqArnoldiOpts), POINTER(c_double), c_void_p,
                              POINTER(c_double), POINTER(FqArnoldiStats), c_void_p]),
     ("arnoldi_eigs_batched", c_int, [POINTER(c_void_p), c_int, POINTER(c_double), c_int, c_int,
-                                     POINTER(FqArnoldiOpts), POINTER(c_double), POINTER(c_void_p),
-                                     POINTER(c_double), POINTER(FqArnoldiStats), c_void_p]),
+                                     POINTER(FqArnoldiOpts), POINTER(c_int), POINTER(c_double),
+                                     POINTER(c_void_p), POINTER(c_double), POINTER(FqArnoldiStats), c_void_p]),
     ("floquet_last_error", ctypes.c_char_p, []),
     ("fq_host_schur", c_int, [c_int, POINTER(c_double), POINTER(c_double), POINTER(c_double)]),
     ("fq_paper_parameters", c_int, [c_int, c_int, POINTER(c_int), POINTER(c_int)]),

@@ -182,25 +182,50 @@ def brickwork(L: int, gates) -> FloquetOp:
     return FloquetOp(desc, keep=(flat,))
 
 
-def arnoldi_eigs_batched(ops: Sequence[FloquetOp], phis: Sequence[float], nev: int, *, k: int, ncv: int,
+def arnoldi_eigs_batched(ops: Sequence[FloquetOp], phis: Sequence[float], nev: int, *, k, ncv: int,
                          tol: float = 1e-10, max_restarts: int = 200, filter_dtype: str = "c128",
-                         refine: bool = True, seed: int = 0, stream=None, allow_not_converged=False):
-    """All (op, phi) problems in one call.  Returns (evals[n_ops, n_phi, nev], resid, stats, status)."""
+                         refine: bool = True, seed: int = 0, want_vectors: bool = False, stream=None,
+                         allow_not_converged=False):
+    """All (op, phi) problems in one call.
+
+    ``k`` is one filter order for every op or a sequence with one per op.
+    Returns (evals[n_ops, n_phi, nev], resid, stats, status), plus the
+    eigenvectors (list over problems of (nev, d) complex128 device tensors)
+    when ``want_vectors``.
+    """
+    torch = _torch()
     n_ops, n_phi = len(ops), len(phis)
     handles = (c_void_p * n_ops)(*[o.handle for o in ops])
     ph, php = _dbl_array(phis)
-    opts = FqArnoldiOpts(k=int(k), ncv=int(ncv), tol=float(tol), max_restarts=int(max_restarts),
+    if np.ndim(k) == 0:
+        kk = None
+        k0 = int(k)
+    else:
+        if len(k) != n_ops:
+            raise ValueError("k needs one entry per op")
+        kk = (ctypes.c_int * n_ops)(*[int(x) for x in k])
+        k0 = int(k[0])
+    opts = FqArnoldiOpts(k=k0, ncv=int(ncv), tol=float(tol), max_restarts=int(max_restarts),
                          filter_dtype=FQ_C64 if filter_dtype == "c64" else FQ_C128,
                          refine=1 if refine else 0, seed=int(seed), v0_dev=None)
     evals = np.zeros(n_ops * n_phi * 2 * nev)
     resid = np.zeros(n_ops * n_phi * nev)
     stats = (FqArnoldiStats * (n_ops * n_phi))()
-    st = lib().arnoldi_eigs_batched(handles, n_ops, php, n_phi, int(nev), ctypes.byref(opts),
-                                    evals.ctypes.data_as(POINTER(c_double)), None,
+    vecs = None
+    vec_ptrs = None
+    if want_vectors:
+        vecs = [torch.empty((nev, ops[i].dim), dtype=torch.complex128, device="cuda")
+                for i in range(n_ops) for _ in range(n_phi)]
+        vec_ptrs = (c_void_p * (n_ops * n_phi))(*[v.data_ptr() for v in vecs])
+    st = lib().arnoldi_eigs_batched(handles, n_ops, php, n_phi, int(nev), ctypes.byref(opts), kk,
+                                    evals.ctypes.data_as(POINTER(c_double)), vec_ptrs,
                                     resid.ctypes.data_as(POINTER(c_double)), stats, _stream_ptr(stream))
     check(st, "arnoldi_eigs_batched", allow=(FQ_OK, FQ_NOT_CONVERGED) if allow_not_converged else (FQ_OK,))
     ev = (evals[0::2] + 1j * evals[1::2]).reshape(n_ops, n_phi, nev)
-    return ev, resid.reshape(n_ops, n_phi, nev), [s.as_dict() for s in stats], st
+    out = (ev, resid.reshape(n_ops, n_phi, nev), [s.as_dict() for s in stats], st)
+    if want_vectors:
+        out = out + (vecs,)
+    return out
 
 
 def host_schur(A: np.ndarray):

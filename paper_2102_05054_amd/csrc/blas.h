@@ -5,6 +5,7 @@
 #pragma once
 
 #include "common.h"
+#include "ki_kernels.h"
 
 namespace fq {
 
@@ -51,5 +52,68 @@ hipError_t launch_basis_gemm(const c128* V, size_t ldv, int m, const c128* Q, in
 hipError_t launch_gram(const c128* X, size_t si, size_t st, bool conj_in, int n, size_t T, c128* G, hipStream_t s);
 // v[i] = counter-based uniform complex in [-1, 1)^2 from (seed, i)
 hipError_t launch_random(c128* v, size_t d, unsigned long long seed, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Batched forms (many independent problems of one size d in one launch).
+// ---------------------------------------------------------------------------
+
+// One problem of a batched Krylov solve (device-resident descriptor).
+struct KDesc {
+  c128* V;         // d x (ncv + 1), column-major, leading dimension d
+  c128* w;         // d
+  c128* partial;   // nblk x ldp
+  double* slots;   // (ncv + 1) x slot_doubles: h1[ncv+1], h2[ncv+1] (complex), beta, 1/beta
+  double* small;   // 16 doubles of scratch (norm, 1/norm)
+};
+
+// Problems kd[list[0..n)] of size d; blockIdx.y walks the list.
+struct BatchArgs {
+  const KDesc* kd;
+  const int* list;
+  unsigned n;
+  size_t d;
+  unsigned nblk;   // row_blocks(d)
+  int ldp;         // ncv + 1
+  int slot_doubles;
+  int ncv;
+};
+
+// Y = V Q (m x p, k-major) for one problem; ld = d for V and Y.  Y may be V.
+struct GemmDesc {
+  const c128* V;
+  c128* Y;
+  const c128* Q;
+  size_t ld;
+  int m, p;
+};
+
+// Ritz pairs of one problem: Y holds the vectors (column i at Y + i*d), u is
+// scratch for U y, partial >= 2 * row_blocks(d) complex, out[4i..4i+3] =
+// (Re omega, Im omega, residual, 1/||y||).
+struct RDesc {
+  c128* Y;
+  c128* u;
+  c128* partial;
+  double* out;
+};
+
+// CGS2 of Arnoldi column j with ncols = j + 1 basis vectors (see arnoldi_step)
+hipError_t launch_b_dots(const BatchArgs& a, int ncols, hipStream_t s);
+hipError_t launch_b_reduce_slot(const BatchArgs& a, int ncols, int j, int which, hipStream_t s);
+hipError_t launch_b_update(const BatchArgs& a, int ncols, int j, int which, hipStream_t s);
+hipError_t launch_b_reduce_norm(const BatchArgs& a, int j, hipStream_t s);
+hipError_t launch_b_scale_next(const BatchArgs& a, int j, hipStream_t s);
+// V[:, col] /= ||V[:, col]||
+hipError_t launch_b_normalize_col(const BatchArgs& a, int col, hipStream_t s);
+// V[:, to] = V[:, from]
+hipError_t launch_b_copy_col(const BatchArgs& a, int from, int to, hipStream_t s);
+// fd[q].psi = V[:, j] in the filter precision; w = fd[q].x (complex64 state)
+template <typename Real>
+hipError_t launch_b_cast_in(const BatchArgs& a, const KiDesc<Real>* fd, int j, hipStream_t s);
+hipError_t launch_b_cast_out(const BatchArgs& a, const KiDesc<float>* fd, hipStream_t s);
+// n basis products on the FP64 matrix cores (p <= 256, d a multiple of 16)
+hipError_t launch_b_basis_gemm(const GemmDesc* g, unsigned n, size_t d, hipStream_t s);
+// Ritz pair i of n problems, after u = U y: omega, residual; y normalised
+hipError_t launch_r_rayleigh(const RDesc* rd, unsigned n, int i, size_t d, hipStream_t s);
 
 }  // namespace fq

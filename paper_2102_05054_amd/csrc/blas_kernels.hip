@@ -42,12 +42,12 @@ __device__ __forceinline__ void block_sum_nch(double (&ax)[NCH], double (&ay)[NC
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(NT) dots_kernel(const c128* __restrict__ V, size_t ldv, int ncols,
-                                                  const c128* __restrict__ w, size_t d, c128* __restrict__ partial,
-                                                  int ldp) {
+__device__ __forceinline__ void dots_body(const c128* __restrict__ V, size_t ldv, int ncols,
+                                          const c128* __restrict__ w, size_t d, c128* __restrict__ partial, int ldp,
+                                          unsigned blk) {
   __shared__ double red[NT / 64][2 * NCH];
   const int tid = threadIdx.x;
-  const size_t r0 = static_cast<size_t>(blockIdx.x) * NT * RPT + tid;
+  const size_t r0 = static_cast<size_t>(blk) * NT * RPT + tid;
   c128 wr[RPT];
   bool ok[RPT];
 #pragma unroll
@@ -82,16 +82,23 @@ __global__ void __launch_bounds__(NT) dots_kernel(const c128* __restrict__ V, si
         sx += red[q][2 * tid];
         sy += red[q][2 * tid + 1];
       }
-      partial[size_t(blockIdx.x) * ldp + i0 + tid] = mk<double>(sx, sy);
+      partial[size_t(blk) * ldp + i0 + tid] = mk<double>(sx, sy);
     }
     __syncthreads();
   }
 }
 
-__global__ void __launch_bounds__(NT) reduce_cols_kernel(const c128* __restrict__ partial, int ldp, unsigned nblk,
-                                                         c128* __restrict__ out) {
+__global__ void __launch_bounds__(NT) dots_kernel(const c128* __restrict__ V, size_t ldv, int ncols,
+                                                  const c128* __restrict__ w, size_t d, c128* __restrict__ partial,
+                                                  int ldp) {
+  dots_body(V, ldv, ncols, w, d, partial, ldp, blockIdx.x);
+}
+
+// out[i] = sum over row blocks of partial[b*ldp + i] (column i of one problem)
+__device__ __forceinline__ void reduce_cols_body(const c128* __restrict__ partial, int ldp, unsigned nblk,
+                                                 c128* __restrict__ out, int i) {
   __shared__ double red[NT / 64][2];
-  const int tid = threadIdx.x, i = blockIdx.x;
+  const int tid = threadIdx.x;
   double sx = 0.0, sy = 0.0;
   for (unsigned b = tid; b < nblk; b += NT) {
     const c128 v = partial[size_t(b) * ldp + i];
@@ -115,16 +122,21 @@ __global__ void __launch_bounds__(NT) reduce_cols_kernel(const c128* __restrict_
   }
 }
 
+__global__ void __launch_bounds__(NT) reduce_cols_kernel(const c128* __restrict__ partial, int ldp, unsigned nblk,
+                                                         c128* __restrict__ out) {
+  reduce_cols_body(partial, ldp, nblk, out, blockIdx.x);
+}
+
 template <bool DOTS, bool NORM>
-__global__ void __launch_bounds__(NT) update_kernel(const c128* __restrict__ V, size_t ldv, int ncols,
-                                                    const c128* __restrict__ h, c128* __restrict__ w, size_t d,
-                                                    c128* __restrict__ partial, int ldp) {
+__device__ __forceinline__ void update_body(const c128* __restrict__ V, size_t ldv, int ncols,
+                                            const c128* __restrict__ h, c128* __restrict__ w, size_t d,
+                                            c128* __restrict__ partial, int ldp, unsigned blk) {
   extern __shared__ c128 hs[];
   __shared__ double red[NT / 64][2 * NCH];
   const int tid = threadIdx.x;
   for (int i = tid; i < ncols; i += NT) hs[i] = h[i];
   __syncthreads();
-  const size_t r0 = static_cast<size_t>(blockIdx.x) * NT * RPT + tid;
+  const size_t r0 = static_cast<size_t>(blk) * NT * RPT + tid;
   c128 acc[RPT];
   bool ok[RPT];
 #pragma unroll
@@ -167,7 +179,7 @@ __global__ void __launch_bounds__(NT) update_kernel(const c128* __restrict__ V, 
     if (tid == 0) {
       double tot = 0.0;
       for (int q = 0; q < NT / 64; ++q) tot += red[q][0];
-      partial[blockIdx.x] = mk<double>(tot, 0.0);
+      partial[blk] = mk<double>(tot, 0.0);
     }
   }
   if constexpr (DOTS) {
@@ -197,17 +209,25 @@ __global__ void __launch_bounds__(NT) update_kernel(const c128* __restrict__ V, 
           sx += red[q][2 * tid];
           sy += red[q][2 * tid + 1];
         }
-        partial[size_t(blockIdx.x) * ldp + i0 + tid] = mk<double>(sx, sy);
+        partial[size_t(blk) * ldp + i0 + tid] = mk<double>(sx, sy);
       }
       __syncthreads();
     }
   }
 }
 
-__global__ void __launch_bounds__(NT) norm2_kernel(const c128* __restrict__ w, size_t d, c128* __restrict__ partial) {
+template <bool DOTS, bool NORM>
+__global__ void __launch_bounds__(NT) update_kernel(const c128* __restrict__ V, size_t ldv, int ncols,
+                                                    const c128* __restrict__ h, c128* __restrict__ w, size_t d,
+                                                    c128* __restrict__ partial, int ldp) {
+  update_body<DOTS, NORM>(V, ldv, ncols, h, w, d, partial, ldp, blockIdx.x);
+}
+
+__device__ __forceinline__ void norm2_body(const c128* __restrict__ w, size_t d, c128* __restrict__ partial,
+                                           unsigned blk) {
   __shared__ double red[NT / 64];
   const int tid = threadIdx.x;
-  const size_t r0 = static_cast<size_t>(blockIdx.x) * NT * RPT + tid;
+  const size_t r0 = static_cast<size_t>(blk) * NT * RPT + tid;
   double s = 0.0;
 #pragma unroll
   for (int t = 0; t < RPT; ++t) {
@@ -223,12 +243,16 @@ __global__ void __launch_bounds__(NT) norm2_kernel(const c128* __restrict__ w, s
   if (tid == 0) {
     double tot = 0.0;
     for (int q = 0; q < NT / 64; ++q) tot += red[q];
-    partial[blockIdx.x] = mk<double>(tot, 0.0);
+    partial[blk] = mk<double>(tot, 0.0);
   }
 }
 
-__global__ void __launch_bounds__(NT) reduce_norm_kernel(const c128* __restrict__ partial, unsigned nblk,
-                                                         double* __restrict__ nrm) {
+__global__ void __launch_bounds__(NT) norm2_kernel(const c128* __restrict__ w, size_t d, c128* __restrict__ partial) {
+  norm2_body(w, d, partial, blockIdx.x);
+}
+
+__device__ __forceinline__ void reduce_norm_body(const c128* __restrict__ partial, unsigned nblk,
+                                                 double* __restrict__ nrm) {
   __shared__ double red[NT / 64];
   const int tid = threadIdx.x;
   double s = 0.0;
@@ -243,6 +267,11 @@ __global__ void __launch_bounds__(NT) reduce_norm_kernel(const c128* __restrict_
     nrm[0] = n;
     nrm[1] = n > 0.0 ? 1.0 / n : 0.0;
   }
+}
+
+__global__ void __launch_bounds__(NT) reduce_norm_kernel(const c128* __restrict__ partial, unsigned nblk,
+                                                         double* __restrict__ nrm) {
+  reduce_norm_body(partial, nblk, nrm);
 }
 
 __global__ void scale_dev_kernel(const c128* __restrict__ in, const double* __restrict__ scale, c128* __restrict__ out,
@@ -308,11 +337,12 @@ __global__ void __launch_bounds__(NT) basis_gemm_kernel(const c128* __restrict__
 // D lane l register r = D[4r + l/16][l%16].
 typedef double fq_d4 __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(64) basis_gemm_mfma_kernel(const c128* __restrict__ V, size_t ldv, int m,
-                                                             const c128* __restrict__ Q, int p, c128* Y, size_t ldy) {
+__device__ __forceinline__ void basis_gemm_mfma_body(const c128* __restrict__ V, size_t ldv, int m,
+                                                     const c128* __restrict__ Q, int p, c128* Y, size_t ldy,
+                                                     unsigned blk) {
   constexpr int MAXT = 16;
   const int l = threadIdx.x;
-  const size_t r0 = static_cast<size_t>(blockIdx.x) * 16;
+  const size_t r0 = static_cast<size_t>(blk) * 16;
   const int ntile = (p + 15) >> 4;
   fq_d4 accr[MAXT], acci[MAXT];
 #pragma unroll
@@ -352,6 +382,11 @@ __global__ void __launch_bounds__(64) basis_gemm_mfma_kernel(const c128* __restr
   }
 }
 
+__global__ void __launch_bounds__(64) basis_gemm_mfma_kernel(const c128* __restrict__ V, size_t ldv, int m,
+                                                             const c128* __restrict__ Q, int p, c128* Y, size_t ldy) {
+  basis_gemm_mfma_body(V, ldv, m, Q, p, Y, ldy, blockIdx.x);
+}
+
 // Gram matrix G[i][j] = sum_t A(i,t) conj(A(j,t)), A(i,t) = X[i*si + t*st]
 // (conjugated if cj): 16x16 output tiles, 64-long t chunks staged in LDS.
 __global__ void __launch_bounds__(256) gram_kernel(const c128* __restrict__ X, size_t si, size_t st, int cj, int n,
@@ -386,6 +421,220 @@ __global__ void __launch_bounds__(256) gram_kernel(const c128* __restrict__ X, s
     __syncthreads();
   }
   if (i0 + ty < n && j0 + tx < n) G[size_t(i0 + ty) * n + (j0 + tx)] = mk<double>(sx, sy);
+}
+
+// ---------------------------------------------------------------------------
+// Batched forms: blockIdx.y selects problem kd[list[blockIdx.y]] (or the
+// descriptor blockIdx.y); each block then runs the single-problem body, so a
+// batched solve does exactly the arithmetic of the single-problem one.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ const KDesc& bprob(const KDesc* kd, const int* list) { return kd[list[blockIdx.y]]; }
+__device__ __forceinline__ c128* slot_c(const KDesc& P, int j, int sd, int off) {
+  return reinterpret_cast<c128*>(P.slots + size_t(j) * sd) + off;
+}
+
+__global__ void __launch_bounds__(NT) b_dots_kernel(const KDesc* kd, const int* list, int ncols, size_t d, int ldp) {
+  const KDesc& P = bprob(kd, list);
+  dots_body(P.V, d, ncols, P.w, d, P.partial, ldp, blockIdx.x);
+}
+
+// h (which = 0: first projection, 1: second) of column j from the partial sums
+__global__ void __launch_bounds__(NT) b_reduce_slot_kernel(const KDesc* kd, const int* list, int ldp, unsigned nblk,
+                                                           int j, int sd, int off) {
+  const KDesc& P = bprob(kd, list);
+  reduce_cols_body(P.partial, ldp, nblk, slot_c(P, j, sd, off), blockIdx.x);
+}
+
+template <bool DOTS, bool NORM>
+__global__ void __launch_bounds__(NT) b_update_kernel(const KDesc* kd, const int* list, int ncols, size_t d, int ldp,
+                                                      int j, int sd, int off) {
+  const KDesc& P = bprob(kd, list);
+  update_body<DOTS, NORM>(P.V, d, ncols, slot_c(P, j, sd, off), P.w, d, P.partial, ldp, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(NT) b_reduce_norm_kernel(const KDesc* kd, const int* list, unsigned nblk, int j,
+                                                           int sd, int off_d) {
+  const KDesc& P = bprob(kd, list);
+  reduce_norm_body(P.partial, nblk, P.slots + size_t(j) * sd + off_d);
+}
+
+// V[:, j+1] = w / beta_j
+__global__ void b_scale_next_kernel(const KDesc* kd, const int* list, size_t d, int j, int sd, int off_d) {
+  const KDesc& P = bprob(kd, list);
+  const double a = P.slots[size_t(j) * sd + off_d + 1];
+  c128* out = P.V + size_t(j + 1) * d;
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < d; i += size_t(gridDim.x) * blockDim.x) {
+    const c128 v = P.w[i];
+    out[i] = mk<double>(v.x * a, v.y * a);
+  }
+}
+
+__global__ void __launch_bounds__(NT) b_norm2_col_kernel(const KDesc* kd, const int* list, size_t d, int col) {
+  const KDesc& P = bprob(kd, list);
+  norm2_body(P.V + size_t(col) * d, d, P.partial, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(NT) b_reduce_norm_small_kernel(const KDesc* kd, const int* list, unsigned nblk) {
+  const KDesc& P = bprob(kd, list);
+  reduce_norm_body(P.partial, nblk, P.small);
+}
+
+__global__ void b_scale_col_kernel(const KDesc* kd, const int* list, size_t d, int col) {
+  const KDesc& P = bprob(kd, list);
+  const double a = P.small[1];
+  c128* v = P.V + size_t(col) * d;
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < d; i += size_t(gridDim.x) * blockDim.x) {
+    const c128 x = v[i];
+    v[i] = mk<double>(x.x * a, x.y * a);
+  }
+}
+
+__global__ void b_copy_col_kernel(const KDesc* kd, const int* list, size_t d, int from, int to) {
+  const KDesc& P = bprob(kd, list);
+  const c128* a = P.V + size_t(from) * d;
+  c128* b = P.V + size_t(to) * d;
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < d; i += size_t(gridDim.x) * blockDim.x) b[i] = a[i];
+}
+
+// filter input: psi (complex64 or complex128 buffer of the problem) = V[:, j]
+template <typename Real>
+__global__ void b_cast_in_kernel(const KDesc* kd, const KiDesc<Real>* fd, const int* list, size_t d, int j) {
+  const int q = list[blockIdx.y];
+  const c128* v = kd[q].V + size_t(j) * d;
+  cpx<Real>* out = const_cast<cpx<Real>*>(fd[q].psi);
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < d; i += size_t(gridDim.x) * blockDim.x)
+    out[i] = mk<Real>(static_cast<Real>(v[i].x), static_cast<Real>(v[i].y));
+}
+
+// filter output (complex64 state x) -> w
+__global__ void b_cast_out_kernel(const KDesc* kd, const KiDesc<float>* fd, const int* list, size_t d) {
+  const int q = list[blockIdx.y];
+  const c64* x = fd[q].x;
+  c128* w = kd[q].w;
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < d; i += size_t(gridDim.x) * blockDim.x)
+    w[i] = mk<double>(x[i].x, x[i].y);
+}
+
+__global__ void __launch_bounds__(64) b_basis_gemm_kernel(const GemmDesc* g) {
+  const GemmDesc& G = g[blockIdx.y];
+  basis_gemm_mfma_body(G.V, G.ld, G.m, G.Q, G.p, G.Y, G.ld, blockIdx.x);
+}
+
+// Ritz pairs: y = Y[:, i] (not yet normalised), u = U y.
+// partial[2b] = sum |y|^2, partial[2b + 1] = sum conj(y) u over block b.
+__global__ void __launch_bounds__(NT) r_dots2_kernel(const RDesc* rd, int i, size_t d) {
+  __shared__ double red[NT / 64][2 * NCH];
+  const RDesc& R = rd[blockIdx.y];
+  const c128* y = R.Y + size_t(i) * d;
+  const int tid = threadIdx.x;
+  const size_t r0 = static_cast<size_t>(blockIdx.x) * NT * RPT + tid;
+  double ax[NCH], ay[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) ax[c] = ay[c] = 0.0;
+#pragma unroll
+  for (int t = 0; t < RPT; ++t) {
+    const size_t r = r0 + size_t(t) * NT;
+    if (r < d) {
+      const c128 a = y[r], b = R.u[r];
+      ax[0] += a.x * a.x + a.y * a.y;
+      ax[1] += a.x * b.x + a.y * b.y;
+      ay[1] += a.x * b.y - a.y * b.x;
+    }
+  }
+  block_sum_nch(ax, ay, red, tid);
+  if (tid < 2) {
+    double sx = 0.0, sy = 0.0;
+#pragma unroll
+    for (int q = 0; q < NT / 64; ++q) {
+      sx += red[q][2 * tid];
+      sy += red[q][2 * tid + 1];
+    }
+    R.partial[2 * size_t(blockIdx.x) + tid] = mk<double>(sx, sy);
+  }
+}
+
+// out[4i..4i+1] = omega = <y|u> / <y|y>, out[4i+3] = 1 / ||y||
+__global__ void __launch_bounds__(NT) r_reduce2_kernel(const RDesc* rd, int i, unsigned nblk) {
+  __shared__ double red[NT / 64][3];
+  const RDesc& R = rd[blockIdx.y];
+  const int tid = threadIdx.x;
+  double yy = 0.0, ux = 0.0, uy = 0.0;
+  for (unsigned b = tid; b < nblk; b += NT) {
+    yy += R.partial[2 * size_t(b)].x;
+    const c128 v = R.partial[2 * size_t(b) + 1];
+    ux += v.x;
+    uy += v.y;
+  }
+  yy = wave_sum(yy);
+  ux = wave_sum(ux);
+  uy = wave_sum(uy);
+  if ((tid & 63) == 0) {
+    red[tid >> 6][0] = yy;
+    red[tid >> 6][1] = ux;
+    red[tid >> 6][2] = uy;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double a = 0.0, bx = 0.0, by = 0.0;
+    for (int q = 0; q < NT / 64; ++q) {
+      a += red[q][0];
+      bx += red[q][1];
+      by += red[q][2];
+    }
+    double* o = R.out + 4 * size_t(i);
+    o[0] = a > 0.0 ? bx / a : 0.0;
+    o[1] = a > 0.0 ? by / a : 0.0;
+    o[3] = a > 0.0 ? 1.0 / sqrt(a) : 0.0;
+  }
+}
+
+// u -= omega y; y /= ||y||; partial[b] = sum |u|^2
+__global__ void __launch_bounds__(NT) r_axpy_norm_kernel(const RDesc* rd, int i, size_t d) {
+  __shared__ double red[NT / 64];
+  const RDesc& R = rd[blockIdx.y];
+  c128* y = R.Y + size_t(i) * d;
+  const double* o = R.out + 4 * size_t(i);
+  const c128 om = mk<double>(o[0], o[1]);
+  const double inv = o[3];
+  const int tid = threadIdx.x;
+  const size_t r0 = static_cast<size_t>(blockIdx.x) * NT * RPT + tid;
+  double s = 0.0;
+#pragma unroll
+  for (int t = 0; t < RPT; ++t) {
+    const size_t r = r0 + size_t(t) * NT;
+    if (r < d) {
+      const c128 a = y[r];
+      const c128 u = csub(R.u[r], cmul(om, a));
+      s += u.x * u.x + u.y * u.y;
+      y[r] = mk<double>(a.x * inv, a.y * inv);
+    }
+  }
+  s = wave_sum(s);
+  if ((tid & 63) == 0) red[tid >> 6] = s;
+  __syncthreads();
+  if (tid == 0) {
+    double tot = 0.0;
+    for (int q = 0; q < NT / 64; ++q) tot += red[q];
+    R.partial[blockIdx.x] = mk<double>(tot, 0.0);
+  }
+}
+
+// out[4i+2] = ||U y - omega y|| / ||y||
+__global__ void __launch_bounds__(NT) r_reduce_rn_kernel(const RDesc* rd, int i, unsigned nblk) {
+  __shared__ double red[NT / 64];
+  const RDesc& R = rd[blockIdx.y];
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  for (unsigned b = tid; b < nblk; b += NT) s += R.partial[b].x;
+  s = wave_sum(s);
+  if ((tid & 63) == 0) red[tid >> 6] = s;
+  __syncthreads();
+  if (tid == 0) {
+    double tot = 0.0;
+    for (int q = 0; q < NT / 64; ++q) tot += red[q];
+    double* o = R.out + 4 * size_t(i);
+    o[2] = sqrt(tot) * o[3];
+  }
 }
 
 __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
@@ -497,6 +746,101 @@ hipError_t launch_gram(const c128* X, size_t si, size_t st, bool conj_in, int n,
 
 hipError_t launch_random(c128* v, size_t d, unsigned long long seed, hipStream_t s) {
   hipLaunchKernelGGL(random_kernel, dim3(grid_for(d)), dim3(256), 0, s, v, d, seed);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched launchers
+// ---------------------------------------------------------------------------
+namespace {
+unsigned grid_rows(size_t d) {
+  const size_t b = (d + 255) / 256;
+  return static_cast<unsigned>(b < 1024 ? (b ? b : 1) : 1024);
+}
+bool batch_ok(const BatchArgs& a) { return a.kd && a.list && a.n > 0 && a.n <= 65535u; }
+}  // namespace
+
+hipError_t launch_b_dots(const BatchArgs& a, int ncols, hipStream_t s) {
+  if (!batch_ok(a)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(b_dots_kernel, dim3(a.nblk, a.n), dim3(NT), 0, s, a.kd, a.list, ncols, a.d, a.ldp);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_reduce_slot(const BatchArgs& a, int ncols, int j, int which, hipStream_t s) {
+  if (!batch_ok(a)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(b_reduce_slot_kernel, dim3(ncols, a.n), dim3(NT), 0, s, a.kd, a.list, a.ldp, a.nblk, j,
+                     a.slot_doubles, which * (a.ncv + 1));
+  return hipGetLastError();
+}
+
+hipError_t launch_b_update(const BatchArgs& a, int ncols, int j, int which, hipStream_t s) {
+  if (!batch_ok(a)) return hipErrorInvalidValue;
+  const size_t sh = sizeof(c128) * ncols;
+  if (which == 0)
+    hipLaunchKernelGGL((b_update_kernel<true, false>), dim3(a.nblk, a.n), dim3(NT), sh, s, a.kd, a.list, ncols, a.d,
+                       a.ldp, j, a.slot_doubles, 0);
+  else
+    hipLaunchKernelGGL((b_update_kernel<false, true>), dim3(a.nblk, a.n), dim3(NT), sh, s, a.kd, a.list, ncols, a.d,
+                       a.ldp, j, a.slot_doubles, a.ncv + 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_reduce_norm(const BatchArgs& a, int j, hipStream_t s) {
+  if (!batch_ok(a)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(b_reduce_norm_kernel, dim3(1, a.n), dim3(NT), 0, s, a.kd, a.list, a.nblk, j, a.slot_doubles,
+                     4 * (a.ncv + 1));
+  return hipGetLastError();
+}
+
+hipError_t launch_b_scale_next(const BatchArgs& a, int j, hipStream_t s) {
+  if (!batch_ok(a)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(b_scale_next_kernel, dim3(grid_rows(a.d), a.n), dim3(256), 0, s, a.kd, a.list, a.d, j,
+                     a.slot_doubles, 4 * (a.ncv + 1));
+  return hipGetLastError();
+}
+
+hipError_t launch_b_normalize_col(const BatchArgs& a, int col, hipStream_t s) {
+  if (!batch_ok(a)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(b_norm2_col_kernel, dim3(a.nblk, a.n), dim3(NT), 0, s, a.kd, a.list, a.d, col);
+  hipLaunchKernelGGL(b_reduce_norm_small_kernel, dim3(1, a.n), dim3(NT), 0, s, a.kd, a.list, a.nblk);
+  hipLaunchKernelGGL(b_scale_col_kernel, dim3(grid_rows(a.d), a.n), dim3(256), 0, s, a.kd, a.list, a.d, col);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_copy_col(const BatchArgs& a, int from, int to, hipStream_t s) {
+  if (!batch_ok(a)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(b_copy_col_kernel, dim3(grid_rows(a.d), a.n), dim3(256), 0, s, a.kd, a.list, a.d, from, to);
+  return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_b_cast_in(const BatchArgs& a, const KiDesc<Real>* fd, int j, hipStream_t s) {
+  if (!batch_ok(a) || !fd) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(b_cast_in_kernel<Real>, dim3(grid_rows(a.d), a.n), dim3(256), 0, s, a.kd, fd, a.list, a.d, j);
+  return hipGetLastError();
+}
+template hipError_t launch_b_cast_in<float>(const BatchArgs&, const KiDesc<float>*, int, hipStream_t);
+template hipError_t launch_b_cast_in<double>(const BatchArgs&, const KiDesc<double>*, int, hipStream_t);
+
+hipError_t launch_b_cast_out(const BatchArgs& a, const KiDesc<float>* fd, hipStream_t s) {
+  if (!batch_ok(a) || !fd) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(b_cast_out_kernel, dim3(grid_rows(a.d), a.n), dim3(256), 0, s, a.kd, fd, a.list, a.d);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_basis_gemm(const GemmDesc* g, unsigned n, size_t d, hipStream_t s) {
+  if (!g || n == 0 || n > 65535u || d % 16 != 0 || d < 16) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(b_basis_gemm_kernel, dim3(static_cast<unsigned>(d / 16), n), dim3(64), 0, s, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_r_rayleigh(const RDesc* rd, unsigned n, int i, size_t d, hipStream_t s) {
+  if (!rd || n == 0 || n > 65535u) return hipErrorInvalidValue;
+  const unsigned nblk = row_blocks(d);
+  hipLaunchKernelGGL(r_dots2_kernel, dim3(nblk, n), dim3(NT), 0, s, rd, i, d);
+  hipLaunchKernelGGL(r_reduce2_kernel, dim3(1, n), dim3(NT), 0, s, rd, i, nblk);
+  hipLaunchKernelGGL(r_axpy_norm_kernel, dim3(nblk, n), dim3(NT), 0, s, rd, i, d);
+  hipLaunchKernelGGL(r_reduce_rn_kernel, dim3(1, n), dim3(NT), 0, s, rd, i, nblk);
   return hipGetLastError();
 }
 

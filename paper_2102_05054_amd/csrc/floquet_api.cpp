@@ -112,6 +112,8 @@ void free_tables(PhaseTables& t) {
   t = PhaseTables{};
 }
 
+}  // namespace
+
 // ---------------------------------------------------------------------------
 // Tile shapes and plans
 // ---------------------------------------------------------------------------
@@ -224,6 +226,8 @@ KiPlan make_plan(int L, bool c64_dt) {
 }
 
 bool single_ok(int L, bool) { return L <= 13; }
+
+namespace {
 
 // ---------------------------------------------------------------------------
 // Kicked-Ising launches

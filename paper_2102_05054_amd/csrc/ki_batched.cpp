@@ -1,0 +1,281 @@
+// Batched kicked-Ising filter / U passes and their tile-shape autotuner.
+#include "ki_batched.h"
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+
+namespace fq {
+
+namespace {
+
+// (RB, TB) pairs with compiled kernel instances (the shape list of the
+// kicked-Ising launchers).
+bool shape_compiled(int rb, int tb) {
+  static const int S[][2] = {{0, 6}, {1, 6}, {2, 6}, {3, 6}, {4, 6}, {4, 7}, {4, 8},
+                             {4, 9}, {1, 7}, {2, 7}, {2, 8}, {3, 8}, {3, 7}, {3, 9}};
+  for (const auto& x : S)
+    if (x[0] == rb && x[1] == tb) return true;
+  return false;
+}
+
+bool group_ok(const KiGroup& g, size_t d) {
+  return g.n >= g.tb && g.rb >= 0 && g.rb + g.tb == g.n && g.rb <= 4 && g.tb <= 9 && g.tb <= g.rb + 6 &&
+         (size_t(g.ntiles) << g.n) == d && shape_compiled(g.rb, g.tb);
+}
+
+bool plan_ok(const KiPlan& p, int L) {
+  if (p.ngroups < 2) return false;
+  for (int i = 0; i < p.ngroups; ++i)
+    if (!group_ok(p.grp[i], size_t(1) << L)) return false;
+  return true;
+}
+
+bool same_plan(const KiPlan& a, const KiPlan& b) {
+  if (a.ngroups != b.ngroups) return false;
+  for (int i = 0; i < a.ngroups; ++i)
+    if (a.grp[i].rb != b.grp[i].rb) return false;
+  return true;
+}
+
+fq_status launch_err(const char* what, hipError_t e) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return FQ_EDEVICE;
+}
+
+template <typename Real>
+fq_status bpass(const KiBatchShape& sh, const KiGroup& g, const KiDesc<Real>* desc, const int* list, unsigned n,
+                int from_psi, int flags, bool k2, hipStream_t s) {
+  KiPassArgs<Real> a{};
+  a.n = g.n;
+  a.c = g.c;
+  a.p = g.p;
+  a.m = sh.m;
+  a.flags = flags;
+  a.psi_coef_re = 1.0;
+  a.in_coef_re = 1.0;
+  // few tiles in the whole launch: latency-bound, fetch the phase with the tile
+  if (size_t(g.ntiles) * n <= (sizeof(Real) == 4 ? 1024u : 512u)) a.flags |= KI_PREFETCH_PHASE;
+  a.k1 = masks_for(g.kbits, g.n, g.rb, g.tb);
+  a.k2 = k2 ? a.k1 : KickMasks{0, 0, 0, 0};
+  a.desc = desc;
+  a.list = list;
+  a.from_psi = from_psi;
+  const hipError_t e = ki_launch_pass<Real>(a, g.rb, g.tb, sh.sw, g.ntiles, s, n);
+  if (e != hipSuccess) return launch_err("batched kicked-Ising pass launch failed", e);
+  return FQ_OK;
+}
+
+template <typename Real>
+fq_status bsingle(const KiBatchShape& sh, const KiDesc<Real>* desc, const int* list, unsigned n, int steps,
+                  int flags, hipStream_t s) {
+  KiSingleArgs<Real> a{};
+  a.in_coef_re = 1.0;
+  a.L = sh.L;
+  a.m = sh.m;
+  a.steps = steps;
+  a.flags = flags;
+  a.kick = masks_for((1u << sh.L) - 1u, std::max(sh.L, 6), sh.srb, sh.stb);
+  a.desc = desc;
+  a.list = list;
+  a.from_psi = 1;
+  const bool regs = (1 << sh.srb) * int(sizeof(cpx<Real>)) <= 128;
+  const hipError_t e = ki_launch_single<Real>(a, sh.srb, sh.stb, sh.sw, regs, n, s, true);
+  if (e != hipSuccess) return launch_err("batched single-tile kicked-Ising launch failed", e);
+  return FQ_OK;
+}
+
+}  // namespace
+
+std::vector<KiBatchShape> ki_batch_candidates(int L, bool sw, bool c64_dt) {
+  std::vector<KiBatchShape> v;
+  KiBatchShape base;
+  base.L = L;
+  base.m = (L + 1) / 2;
+  base.sw = sw;
+  if (L <= 13) {
+    int rb, tb;
+    single_shape(L, &rb, &tb);
+    for (int delta : {0, 1, -1}) {
+      int t = tb + delta, r = L - t;
+      if (L < 6) {
+        if (delta != 0) continue;
+        t = 6;
+        r = 0;
+      }
+      if (r < 0 || r > 4 || t < 6 || t > 9 || t > r + 6 || !shape_compiled(r, t)) continue;
+      KiBatchShape c = base;
+      c.single = true;
+      c.srb = r;
+      c.stb = t;
+      v.push_back(c);
+    }
+  }
+  const KiPlan pl = make_plan(L, c64_dt);
+  std::vector<KiPlan> plans;
+  if (plan_ok(pl, L)) plans.push_back(pl);
+  for (int rbv : {4, 3, 2}) {
+    KiPlan q = pl;
+    for (int i = 0; i < q.ngroups; ++i) {
+      KiGroup& g = q.grp[i];
+      const int tb = g.n - rbv;
+      if (tb >= 6 && tb <= 9 && tb <= rbv + 6 && shape_compiled(rbv, tb)) {
+        g.rb = rbv;
+        g.tb = tb;
+      }
+    }
+    if (!plan_ok(q, L)) continue;
+    bool dup = false;
+    for (const KiPlan& o : plans) dup = dup || same_plan(o, q);
+    if (!dup) plans.push_back(q);
+  }
+  for (const KiPlan& q : plans) {
+    KiBatchShape c = base;
+    c.plan = q;
+    v.push_back(c);
+  }
+  return v;
+}
+
+template <typename Real>
+fq_status ki_batch_filter(const KiBatchShape& sh, int k, const KiDesc<Real>* desc, const int* list, unsigned n,
+                          hipStream_t s) {
+  if (n == 0) return FQ_OK;
+  if (k < 1) {
+    set_error("internal: batched filter needs k >= 1");
+    return FQ_EINVAL;
+  }
+  if (sh.single) return bsingle<Real>(sh, desc, list, n, k, KI_ADD_PSI, s);
+  const KiPlan& pl = sh.plan;
+  if (!plan_ok(pl, sh.L)) {
+    set_error("internal: inconsistent batched kicked-Ising tile plan");
+    return FQ_EINVAL;
+  }
+  fq_status st;
+  if (pl.ngroups == 2) {
+    // prologue: kick of the second group on psi; then alternate the groups
+    st = bpass<Real>(sh, pl.grp[1], desc, list, n, 1, 0, false, s);
+    if (st != FQ_OK) return st;
+    for (int step = 1; step <= k; ++step) {
+      st = bpass<Real>(sh, pl.grp[(step - 1) & 1], desc, list, n, 0, KI_PHASE | KI_ADD_PSI, step < k, s);
+      if (st != FQ_OK) return st;
+    }
+    return FQ_OK;
+  }
+  for (int step = 1; step <= k; ++step) {
+    st = bpass<Real>(sh, pl.grp[2], desc, list, n, step == 1 ? 1 : 0, 0, false, s);
+    if (st != FQ_OK) return st;
+    st = bpass<Real>(sh, pl.grp[1], desc, list, n, 0, 0, false, s);
+    if (st != FQ_OK) return st;
+    st = bpass<Real>(sh, pl.grp[0], desc, list, n, 0, KI_PHASE | KI_ADD_PSI, false, s);
+    if (st != FQ_OK) return st;
+  }
+  return FQ_OK;
+}
+
+template <typename Real>
+fq_status ki_batch_apply(const KiBatchShape& sh, const KiDesc<Real>* desc, const int* list, unsigned n,
+                         hipStream_t s) {
+  if (n == 0) return FQ_OK;
+  if (sh.single) return bsingle<Real>(sh, desc, list, n, 1, 0, s);
+  const KiPlan& pl = sh.plan;
+  if (!plan_ok(pl, sh.L)) {
+    set_error("internal: inconsistent batched kicked-Ising tile plan");
+    return FQ_EINVAL;
+  }
+  for (int gi = pl.ngroups - 1; gi >= 0; --gi) {
+    const fq_status st =
+        bpass<Real>(sh, pl.grp[gi], desc, list, n, gi == pl.ngroups - 1 ? 1 : 0, gi == 0 ? KI_PHASE : 0, false, s);
+    if (st != FQ_OK) return st;
+  }
+  return FQ_OK;
+}
+
+namespace {
+std::mutex g_tune_mu;
+std::map<std::tuple<int, bool, bool, int, int>, KiBatchShape> g_tuned;
+
+int size_class(unsigned n) {
+  int c = 0;
+  while ((1u << c) < n) ++c;
+  return c;
+}
+}  // namespace
+
+template <typename Real>
+fq_status ki_batch_tune(int L, bool sw, int k, const KiDesc<Real>* desc, const int* list, unsigned n,
+                        hipStream_t s, KiBatchShape* out, double* best_us) {
+  const bool c64_dt = sizeof(Real) == 4;
+  const auto key = std::make_tuple(L, sw, c64_dt, k, size_class(n));
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+      *out = it->second;
+      if (best_us) *best_us = -1.0;
+      return FQ_OK;
+    }
+  }
+  const std::vector<KiBatchShape> cands = ki_batch_candidates(L, sw, c64_dt);
+  if (cands.empty()) {
+    set_error("no kicked-Ising tile shape for L = " + std::to_string(L));
+    return FQ_EINVAL;
+  }
+  int best = 0;
+  double best_t = -1.0;
+  if (cands.size() > 1) {
+    const int kt = std::min(k, 32);
+    hipEvent_t e0, e1;
+    FQ_HIP_CHECK(hipEventCreate(&e0));
+    FQ_HIP_CHECK(hipEventCreate(&e1));
+    for (size_t c = 0; c < cands.size(); ++c) {
+      if (ki_batch_filter<Real>(cands[c], kt, desc, list, n, s) != FQ_OK) {
+        (void)hipGetLastError();
+        continue;
+      }
+      (void)hipEventRecord(e0, s);
+      bool ok = true;
+      for (int r = 0; r < 2 && ok; ++r) ok = ki_batch_filter<Real>(cands[c], kt, desc, list, n, s) == FQ_OK;
+      (void)hipEventRecord(e1, s);
+      if (hipEventSynchronize(e1) != hipSuccess || !ok) {
+        (void)hipGetLastError();
+        continue;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      const double us = 1000.0 * ms / (2.0 * kt);
+      if (best_t < 0.0 || us < best_t) {
+        best_t = us;
+        best = static_cast<int>(c);
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best_t < 0.0) {
+      set_error("no kicked-Ising tile shape could be launched for L = " + std::to_string(L));
+      return FQ_EDEVICE;
+    }
+  }
+  *out = cands[best];
+  if (best_us) *best_us = best_t;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tuned[key] = cands[best];
+  return FQ_OK;
+}
+
+template fq_status ki_batch_filter<float>(const KiBatchShape&, int, const KiDesc<float>*, const int*, unsigned,
+                                          hipStream_t);
+template fq_status ki_batch_filter<double>(const KiBatchShape&, int, const KiDesc<double>*, const int*, unsigned,
+                                           hipStream_t);
+template fq_status ki_batch_apply<float>(const KiBatchShape&, const KiDesc<float>*, const int*, unsigned,
+                                         hipStream_t);
+template fq_status ki_batch_apply<double>(const KiBatchShape&, const KiDesc<double>*, const int*, unsigned,
+                                          hipStream_t);
+template fq_status ki_batch_tune<float>(int, bool, int, const KiDesc<float>*, const int*, unsigned, hipStream_t,
+                                        KiBatchShape*, double*);
+template fq_status ki_batch_tune<double>(int, bool, int, const KiDesc<double>*, const int*, unsigned, hipStream_t,
+                                         KiBatchShape*, double*);
+
+}  // namespace fq

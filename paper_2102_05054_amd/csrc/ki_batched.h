@@ -1,0 +1,45 @@
+// Batched kicked-Ising filter and U passes: many independent problems of one
+// chain length L (own couplings, own target phase, own vectors) advanced
+// together, one launch per Horner pass for the whole batch.
+#pragma once
+
+#include <vector>
+
+#include "op.h"
+
+namespace fq {
+
+// How a batch applies U: one workgroup per problem running all k steps in
+// one launch (small L), or the multi-pass tile plan with one launch per pass
+// covering every problem (blockIdx.y = problem).
+struct KiBatchShape {
+  int L = 0, m = 0;
+  bool sw = false;
+  bool single = false;
+  int srb = 0, stb = 0;  // single-workgroup tile
+  KiPlan plan;           // multi-pass plan
+};
+
+// Candidate shapes for (L, kick form, precision), the default first.
+std::vector<KiBatchShape> ki_batch_candidates(int L, bool sw, bool c64_dt);
+
+// x_q = g_k(U_q) psi_q for the problems desc[list[0..n)] (geometric sum; the
+// rotation e^{-i phi_q} and the kick scales live in each problem's tables).
+template <typename Real>
+fq_status ki_batch_filter(const KiBatchShape& sh, int k, const KiDesc<Real>* desc, const int* list, unsigned n,
+                          hipStream_t s);
+
+// x_q = U_q psi_q.
+template <typename Real>
+fq_status ki_batch_apply(const KiBatchShape& sh, const KiDesc<Real>* desc, const int* list, unsigned n,
+                         hipStream_t s);
+
+// Autotuner: times every candidate shape on the given problems (their psi and
+// x buffers are overwritten) for min(k, 32) Horner steps and returns the
+// fastest; results are cached per (L, kick form, precision, k, batch size
+// class).  best_us (optional) receives the time per Horner step of the batch.
+template <typename Real>
+fq_status ki_batch_tune(int L, bool sw, int k, const KiDesc<Real>* desc, const int* list, unsigned n,
+                        hipStream_t s, KiBatchShape* out, double* best_us);
+
+}  // namespace fq

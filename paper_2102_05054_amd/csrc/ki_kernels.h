@@ -19,6 +19,19 @@ struct KickMasks {
   unsigned regA, laneA, regB, laneB;
 };
 
+// Per-problem pointers of a batched launch (one problem per blockIdx.y of a
+// pass, per workgroup of the single-tile kernel): psi, the state x, the phase
+// tables and the butterfly weight of that problem's operator.
+template <typename Real>
+struct KiDesc {
+  const cpx<Real>* psi;
+  cpx<Real>* x;
+  const cpx<Real>* tlo;
+  const cpx<Real>* thi;
+  double w;
+  double pad;
+};
+
 template <typename Real>
 struct KiPassArgs {
   const cpx<Real>* xin;
@@ -32,6 +45,11 @@ struct KiPassArgs {
   int n, c, p, m;           // tile bits, chunk bits, position of the high run, table split
   int flags;
   KickMasks k1, k2;         // before / after the phase
+  // batched launches: problem desc[list[blockIdx.y]]; the pass reads psi
+  // (from_psi) or x and writes x
+  const KiDesc<Real>* desc;
+  const int* list;
+  int from_psi;
 };
 
 template <typename Real>
@@ -47,13 +65,20 @@ struct KiSingleArgs {
   size_t batch_stride;      // amplitudes between problems (blockIdx.x)
   int L, m, steps, flags;
   KickMasks kick;
+  // batched launches: workgroup b runs problem desc[list[b]], reading psi
+  // (from_psi) or x and writing x
+  const KiDesc<Real>* desc;
+  const int* list;
+  int from_psi;
 };
 
+// nprob > 0 selects the batched kernels (a.desc / a.list, nprob problems).
 template <typename Real>
-hipError_t ki_launch_pass(const KiPassArgs<Real>& a, int rb, int tb, bool sw, unsigned ntiles, hipStream_t s);
+hipError_t ki_launch_pass(const KiPassArgs<Real>& a, int rb, int tb, bool sw, unsigned ntiles, hipStream_t s,
+                          unsigned nprob = 0);
 template <typename Real>
 hipError_t ki_launch_single(const KiSingleArgs<Real>& a, int rb, int tb, bool sw, bool psi_regs,
-                            unsigned nblocks, hipStream_t s);
+                            unsigned nblocks, hipStream_t s, bool batched = false);
 
 hipError_t launch_cast_c128_to_c64(const void* in, void* out, size_t n, hipStream_t s);
 hipError_t launch_cast_c64_to_c128(const void* in, void* out, size_t n, hipStream_t s);

@@ -20,6 +20,11 @@
 // next:  K_S -> D -> +psi -> K_S.  Passes alternate between the groups; a
 // prologue applies the other group's kick to psi and the last pass omits the
 // trailing kick.  One pass = one Horner step = read w, read psi, write w.
+//
+// Kernel templates and launchers; ki_kernels_f32.hip / ki_kernels_f64.hip
+// instantiate them per precision (two translation units build in parallel).
+#pragma once
+
 #include "tile_engine.h"
 #include "ki_kernels.h"
 
@@ -115,7 +120,7 @@ __device__ __forceinline__ cpx<Real> ki_phase(const cpx<Real>* __restrict__ tlo,
 // ---------------------------------------------------------------------------
 // One pass over all tiles of one group (see ki_kernels.h for the fields).
 // ---------------------------------------------------------------------------
-template <typename Real, int RB, int TB, bool SW, bool PF>
+template <typename Real, int RB, int TB, bool SW, bool PF, bool BATCH>
 __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
   using C = cpx<Real>;
   constexpr int R = 1 << RB;
@@ -124,7 +129,28 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
   const int tid = threadIdx.x;
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const TileMap tm = make_tile_map(tile, a.n, a.c, a.p);
-  const Real w = static_cast<Real>(a.w);
+  const C* __restrict__ xin;
+  C* __restrict__ xout;
+  const C* __restrict__ psi;
+  const C* __restrict__ tlo;
+  const C* __restrict__ thi;
+  Real w;
+  if constexpr (BATCH) {
+    const KiDesc<Real>& D = a.desc[a.list[blockIdx.y]];
+    xin = a.from_psi ? D.psi : D.x;
+    xout = D.x;
+    psi = D.psi;
+    tlo = D.tlo;
+    thi = D.thi;
+    w = static_cast<Real>(D.w);
+  } else {
+    xin = a.xin;
+    xout = a.xout;
+    psi = a.psi;
+    tlo = a.tlo;
+    thi = a.thi;
+    w = static_cast<Real>(a.w);
+  }
   const bool do_ph = (a.flags & KI_PHASE) != 0;
   const bool do_ps = (a.flags & KI_ADD_PSI) != 0;
 
@@ -133,10 +159,10 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
   // so every global access of the pass is coalesced.
   C v[R], ps[R], tl[PF ? R : 1], th[PF ? R : 1];
 #pragma unroll
-  for (int m = 0; m < R; ++m) v[m] = a.xin[tm.g(tid + (m << TB))];
+  for (int m = 0; m < R; ++m) v[m] = xin[tm.g(tid + (m << TB))];
   if (do_ps) {
 #pragma unroll
-    for (int m = 0; m < R; ++m) ps[m] = a.psi[tm.g(tid + (m << TB))];
+    for (int m = 0; m < R; ++m) ps[m] = psi[tm.g(tid + (m << TB))];
   }
   // with few tiles per CU (small states) the pass is latency-bound: fetch the
   // phase-table entries together with the tile instead of mid-pass
@@ -145,8 +171,8 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
 #pragma unroll
     for (int m = 0; m < R; ++m) {
       const uint32_t g = tm.g(tid + (m << TB));
-      tl[m] = a.tlo[g & ((1u << a.m) - 1u)];
-      th[m] = a.thi[((g >> a.m) << 2) | ((g & 1u) << 1) | ((g >> (a.m - 1)) & 1u)];
+      tl[m] = tlo[g & ((1u << a.m) - 1u)];
+      th[m] = thi[((g >> a.m) << 2) | ((g & 1u) << 1) | ((g >> (a.m - 1)) & 1u)];
     }
   }
   if (a.flags & KI_SCALE_IN) {
@@ -175,7 +201,7 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
       if constexpr (pre_ph) {
         if (do_ph) x = cmul(x, cmul(tl[m], th[m]));
       } else {
-        if (do_ph) x = cmul(x, ki_phase(a.tlo, a.thi, tm.g(tid + (m << TB)), a.m));
+        if (do_ph) x = cmul(x, ki_phase(tlo, thi, tm.g(tid + (m << TB)), a.m));
       }
       if (do_ps) x = coef ? cfma(ps[m], pc, x) : cadd(x, ps[m]);
       v[m] = x;
@@ -195,7 +221,7 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
   }
 
 #pragma unroll
-  for (int m = 0; m < R; ++m) a.xout[tm.g(tid + (m << TB))] = v[m];
+  for (int m = 0; m < R; ++m) xout[tm.g(tid + (m << TB))] = v[m];
 }
 
 // ---------------------------------------------------------------------------
@@ -206,20 +232,39 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
 // coefs (device, k entries, may be NULL): coefficient of psi in step s, used
 // for general polynomials; NULL means 1.
 // ---------------------------------------------------------------------------
-template <typename Real, int RB, int TB, bool SW, bool PSI_REGS>
+template <typename Real, int RB, int TB, bool SW, bool PSI_REGS, bool BATCH>
 __global__ void __launch_bounds__(1 << TB) ki_single_kernel(KiSingleArgs<Real> a) {
   using C = cpx<Real>;
   constexpr int R = 1 << RB;
   extern __shared__ char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
   const int tid = threadIdx.x;
-  const Real w = static_cast<Real>(a.w);
   const uint32_t dim = 1u << a.L;
-  // problem offset for batched launches (one workgroup per problem)
-  const size_t off = static_cast<size_t>(blockIdx.x) * a.batch_stride;
-  const C* __restrict__ psi = a.psi + off;
-  const C* __restrict__ xin = a.xin + off;
-  C* __restrict__ xout = a.xout + off;
+  const C* __restrict__ psi;
+  const C* __restrict__ xin;
+  C* __restrict__ xout;
+  const C* __restrict__ tlo;
+  const C* __restrict__ thi;
+  Real w;
+  if constexpr (BATCH) {
+    // one workgroup per problem of the list
+    const KiDesc<Real>& D = a.desc[a.list[blockIdx.x]];
+    psi = D.psi;
+    xin = a.from_psi ? D.psi : D.x;
+    xout = D.x;
+    tlo = D.tlo;
+    thi = D.thi;
+    w = static_cast<Real>(D.w);
+  } else {
+    // problems at a fixed stride (one workgroup each)
+    const size_t off = static_cast<size_t>(blockIdx.x) * a.batch_stride;
+    psi = a.psi + off;
+    xin = a.xin + off;
+    xout = a.xout + off;
+    tlo = a.tlo;
+    thi = a.thi;
+    w = static_cast<Real>(a.w);
+  }
 
   // layout B: tid*R + m
   C v[R];
@@ -232,7 +277,7 @@ __global__ void __launch_bounds__(1 << TB) ki_single_kernel(KiSingleArgs<Real> a
     v[m] = active ? xin[g] : mk<Real>(0, 0);
     if constexpr (PSI_REGS) {
       ps[m] = active ? psi[g] : mk<Real>(0, 0);
-      ph[m] = active ? ki_phase(a.tlo, a.thi, g, a.m) : mk<Real>(0, 0);
+      ph[m] = active ? ki_phase(tlo, thi, g, a.m) : mk<Real>(0, 0);
     }
   }
   if (a.flags & KI_SCALE_IN) {
@@ -266,7 +311,7 @@ __global__ void __launch_bounds__(1 << TB) ki_single_kernel(KiSingleArgs<Real> a
       if constexpr (PSI_REGS)
         x = cmul(v[m], ph[m]);
       else
-        x = active ? cmul(v[m], ki_phase(a.tlo, a.thi, (tid << RB) + m, a.m)) : v[m];
+        x = active ? cmul(v[m], ki_phase(tlo, thi, (tid << RB) + m, a.m)) : v[m];
       if (a.flags & KI_ADD_PSI) {
         C p;
         if constexpr (PSI_REGS)
@@ -285,26 +330,14 @@ __global__ void __launch_bounds__(1 << TB) ki_single_kernel(KiSingleArgs<Real> a
 }
 
 // ---------------------------------------------------------------------------
-// Casts between complex128 and complex64 (mixed-precision filter).
-// ---------------------------------------------------------------------------
-__global__ void cast_c128_to_c64(const c128* __restrict__ in, c64* __restrict__ out, size_t n) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    out[i] = mk<float>(static_cast<float>(in[i].x), static_cast<float>(in[i].y));
-}
-__global__ void cast_c64_to_c128(const c64* __restrict__ in, c128* __restrict__ out, size_t n) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    out[i] = mk<double>(in[i].x, in[i].y);
-}
-
-// ---------------------------------------------------------------------------
 // Host launchers: runtime (RB, TB, SW) -> template instance.
 // ---------------------------------------------------------------------------
 namespace {
 
-template <typename Real, int RB, int TB, bool SW, bool PF>
-hipError_t launch_pass_t(const KiPassArgs<Real>& a, unsigned ntiles, hipStream_t s) {
+template <typename Real, int RB, int TB, bool SW, bool PF, bool BATCH>
+hipError_t launch_pass_t(const KiPassArgs<Real>& a, unsigned ntiles, unsigned nprob, hipStream_t s) {
   const size_t shmem = static_cast<size_t>(lds_slots<RB, TB>()) * sizeof(cpx<Real>);
-  auto kern = ki_pass_kernel<Real, RB, TB, SW, PF>;
+  auto kern = ki_pass_kernel<Real, RB, TB, SW, PF, BATCH>;
   static bool attr_set = false;
   if (!attr_set && shmem > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -312,35 +345,33 @@ hipError_t launch_pass_t(const KiPassArgs<Real>& a, unsigned ntiles, hipStream_t
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(kern, dim3(ntiles), dim3(1 << TB), shmem, s, a);
+  hipLaunchKernelGGL(kern, dim3(ntiles, BATCH ? nprob : 1u), dim3(1 << TB), shmem, s, a);
+  return hipGetLastError();
+}
+
+template <typename Real, int RB, int TB, bool SW, bool PSI_REGS, bool BATCH>
+hipError_t launch_single_tt(const KiSingleArgs<Real>& a, unsigned nblocks, hipStream_t s) {
+  const size_t shmem = static_cast<size_t>(lds_slots<RB, TB>()) * sizeof(cpx<Real>);
+  auto kern = ki_single_kernel<Real, RB, TB, SW, PSI_REGS, BATCH>;
+  static bool attr_set = false;
+  if (!attr_set && shmem > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(kern, dim3(nblocks), dim3(1 << TB), shmem, s, a);
   return hipGetLastError();
 }
 
 template <typename Real, int RB, int TB, bool SW>
-hipError_t launch_single_t(const KiSingleArgs<Real>& a, unsigned nblocks, bool psi_regs, hipStream_t s) {
-  const size_t shmem = static_cast<size_t>(lds_slots<RB, TB>()) * sizeof(cpx<Real>);
-  if (psi_regs) {
-    auto kern = ki_single_kernel<Real, RB, TB, SW, true>;
-    static bool attr_set = false;
-    if (!attr_set && shmem > 65536) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem));
-      if (e != hipSuccess) return e;
-      attr_set = true;
-    }
-    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(1 << TB), shmem, s, a);
-  } else {
-    auto kern = ki_single_kernel<Real, RB, TB, SW, false>;
-    static bool attr_set = false;
-    if (!attr_set && shmem > 65536) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem));
-      if (e != hipSuccess) return e;
-      attr_set = true;
-    }
-    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(1 << TB), shmem, s, a);
-  }
-  return hipGetLastError();
+hipError_t launch_single_t(const KiSingleArgs<Real>& a, unsigned nblocks, bool psi_regs, bool batched,
+                           hipStream_t s) {
+  if (batched)
+    return psi_regs ? launch_single_tt<Real, RB, TB, SW, true, true>(a, nblocks, s)
+                    : launch_single_tt<Real, RB, TB, SW, false, true>(a, nblocks, s);
+  return psi_regs ? launch_single_tt<Real, RB, TB, SW, true, false>(a, nblocks, s)
+                  : launch_single_tt<Real, RB, TB, SW, false, false>(a, nblocks, s);
 }
 
 }  // namespace
@@ -348,50 +379,40 @@ hipError_t launch_single_t(const KiSingleArgs<Real>& a, unsigned nblocks, bool p
 #define FQ_SHAPES(X) X(0, 6) X(1, 6) X(2, 6) X(3, 6) X(4, 6) X(4, 7) X(4, 8) X(4, 9) X(1, 7) X(2, 7) X(2, 8) X(3, 8) X(3, 7) X(3, 9)
 
 template <typename Real>
-hipError_t ki_launch_pass(const KiPassArgs<Real>& a, int rb, int tb, bool sw, unsigned ntiles, hipStream_t s) {
+hipError_t ki_launch_pass(const KiPassArgs<Real>& a, int rb, int tb, bool sw, unsigned ntiles, hipStream_t s,
+                          unsigned nprob) {
   const bool pf = (a.flags & KI_PREFETCH_PHASE) != 0;
+  if (nprob > 0 && (!a.desc || !a.list || nprob > 65535u)) return hipErrorInvalidValue;
+#define FQ_CASE4(RB_, TB_, PF_)                                                                    \
+  if (nprob > 0)                                                                                   \
+    return sw ? launch_pass_t<Real, RB_, TB_, true, PF_, true>(a, ntiles, nprob, s)                \
+              : launch_pass_t<Real, RB_, TB_, false, PF_, true>(a, ntiles, nprob, s);              \
+  return sw ? launch_pass_t<Real, RB_, TB_, true, PF_, false>(a, ntiles, 1, s)                     \
+            : launch_pass_t<Real, RB_, TB_, false, PF_, false>(a, ntiles, 1, s);
 #define FQ_CASE(RB_, TB_)                                                                          \
   if (rb == RB_ && tb == TB_) {                                                                    \
-    if (pf)                                                                                        \
-      return sw ? launch_pass_t<Real, RB_, TB_, true, true>(a, ntiles, s)                          \
-                : launch_pass_t<Real, RB_, TB_, false, true>(a, ntiles, s);                        \
-    return sw ? launch_pass_t<Real, RB_, TB_, true, false>(a, ntiles, s)                           \
-              : launch_pass_t<Real, RB_, TB_, false, false>(a, ntiles, s);                         \
+    if (pf) {                                                                                      \
+      FQ_CASE4(RB_, TB_, true)                                                                     \
+    }                                                                                              \
+    FQ_CASE4(RB_, TB_, false)                                                                      \
   }
   FQ_SHAPES(FQ_CASE)
 #undef FQ_CASE
+#undef FQ_CASE4
   return hipErrorInvalidValue;
 }
 
 template <typename Real>
 hipError_t ki_launch_single(const KiSingleArgs<Real>& a, int rb, int tb, bool sw, bool psi_regs,
-                            unsigned nblocks, hipStream_t s) {
-#define FQ_CASE(RB_, TB_)                                                          \
-  if (rb == RB_ && tb == TB_)                                                      \
-    return sw ? launch_single_t<Real, RB_, TB_, true>(a, nblocks, psi_regs, s)     \
-              : launch_single_t<Real, RB_, TB_, false>(a, nblocks, psi_regs, s);
+                            unsigned nblocks, hipStream_t s, bool batched) {
+  if (batched && (!a.desc || !a.list)) return hipErrorInvalidValue;
+#define FQ_CASE(RB_, TB_)                                                                   \
+  if (rb == RB_ && tb == TB_)                                                               \
+    return sw ? launch_single_t<Real, RB_, TB_, true>(a, nblocks, psi_regs, batched, s)     \
+              : launch_single_t<Real, RB_, TB_, false>(a, nblocks, psi_regs, batched, s);
   FQ_SHAPES(FQ_CASE)
 #undef FQ_CASE
   return hipErrorInvalidValue;
-}
-
-template hipError_t ki_launch_pass<float>(const KiPassArgs<float>&, int, int, bool, unsigned, hipStream_t);
-template hipError_t ki_launch_pass<double>(const KiPassArgs<double>&, int, int, bool, unsigned, hipStream_t);
-template hipError_t ki_launch_single<float>(const KiSingleArgs<float>&, int, int, bool, bool, unsigned, hipStream_t);
-template hipError_t ki_launch_single<double>(const KiSingleArgs<double>&, int, int, bool, bool, unsigned,
-                                             hipStream_t);
-
-hipError_t launch_cast_c128_to_c64(const void* in, void* out, size_t n, hipStream_t s) {
-  const unsigned blocks = static_cast<unsigned>(std::min<size_t>((n + 255) / 256, 8192));
-  hipLaunchKernelGGL(cast_c128_to_c64, dim3(blocks ? blocks : 1), dim3(256), 0, s,
-                     static_cast<const c128*>(in), static_cast<c64*>(out), n);
-  return hipGetLastError();
-}
-hipError_t launch_cast_c64_to_c128(const void* in, void* out, size_t n, hipStream_t s) {
-  const unsigned blocks = static_cast<unsigned>(std::min<size_t>((n + 255) / 256, 8192));
-  hipLaunchKernelGGL(cast_c64_to_c128, dim3(blocks ? blocks : 1), dim3(256), 0, s,
-                     static_cast<const c64*>(in), static_cast<c128*>(out), n);
-  return hipGetLastError();
 }
 
 }  // namespace fq

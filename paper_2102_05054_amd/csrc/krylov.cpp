@@ -32,9 +32,66 @@
 
 #include "blas.h"
 #include "dense.h"
+#include "krylov.h"
 #include "op.h"
 
 namespace fq {
+
+// Schur form of S = H[0:mm, 0:mm] with the nsort largest |theta| first,
+// b^T Z, and the Ritz coefficient vectors / relative estimates of the nev
+// wanted pairs.
+int keep_count(int m, int nev) { return std::min(m - 1, std::max(nev + 1, nev + (m - nev) / 2)); }
+
+void warm_start_coefs(unsigned long long seed, int nev, std::vector<c128>* cc) {
+  cc->assign(static_cast<size_t>(nev), c128{});
+  uint64_t x = seed * 0x9E3779B97F4A7C15ull + 12345;
+  for (int i = 0; i < nev; ++i) {
+    x ^= x << 13;
+    x ^= x >> 7;
+    x ^= x << 17;
+    const double ang = double(x >> 11) * (2.0 * M_PI / 9007199254740992.0);
+    (*cc)[i] = mk<double>(std::cos(ang), std::sin(ang));
+  }
+}
+
+fq_status analyse_decomposition(const ZMat& H, int mm, int nsort, int nev, double tolg, ZMat* T, ZMat* Z,
+                              std::vector<zd>* bz, ZMat* X, int* nconv, double* worst) {
+  *T = ZMat(mm, mm);
+  for (int j = 0; j < mm; ++j)
+    for (int i = 0; i < mm; ++i) (*T)(i, j) = H(i, j);
+  if (!schur(*T, *Z)) {
+    set_error("QR iteration on the projected matrix did not converge");
+    return FQ_ENUMERIC;
+  }
+  schur_sort(*T, *Z, std::min(nsort, mm), [](const zd& a, const zd& b) { return std::abs(a) > std::abs(b); });
+  bz->assign(mm, zd(0, 0));
+  for (int c = 0; c < mm; ++c) {
+    zd acc = 0;
+    for (int i = 0; i < mm; ++i) acc += H(mm, i) * (*Z)(i, c);
+    (*bz)[c] = acc;
+  }
+  *nconv = 0;
+  *worst = 0.0;
+  *X = ZMat(mm, nev);
+  for (int i = 0; i < nev; ++i) {
+    std::vector<zd> y = tri_eigvec(*T, i);
+    double yn = 0.0;
+    for (const zd& v : y) yn += std::norm(v);
+    yn = std::sqrt(yn);
+    zd e = 0;
+    for (int l = 0; l <= i; ++l) e += (*bz)[l] * y[l];
+    const double est = std::abs(e) / (yn * std::max(std::abs((*T)(i, i)), 1e-300));
+    *worst = std::max(*worst, est);
+    if (est <= tolg) ++*nconv;
+    for (int r = 0; r < mm; ++r) {
+      zd acc = 0;
+      for (int l = 0; l <= i; ++l) acc += (*Z)(r, l) * y[l];
+      (*X)(r, i) = acc / yn;
+    }
+  }
+  return FQ_OK;
+}
+
 
 namespace {
 
@@ -242,7 +299,7 @@ struct Solver {
     const int m = ncv;
     ZMat H(m + 1, m);
     int kk = 0;
-    const int p_keep = std::min(m - 1, std::max(nev + 1, nev + (m - nev) / 2));
+    const int p_keep = keep_count(m, nev);
     const int check_every = std::max(4, m / 16);
     double best = 1e300;
     int stall = 0;
@@ -358,51 +415,18 @@ struct Solver {
     }
   }
 
-  // Schur form of S = H[0:mm, 0:mm] with the nsort largest |theta| first,
-  // b^T Z, and the Ritz coefficient vectors / relative estimates of the nev
-  // wanted pairs.
   fq_status analyse(const ZMat& H, int mm, int nsort, double tolg, ZMat* T, ZMat* Z, std::vector<zd>* bz, ZMat* X,
                     int* nconv, double* worst) {
     const double t2 = now_s();
-    *T = ZMat(mm, mm);
-    for (int j = 0; j < mm; ++j)
-      for (int i = 0; i < mm; ++i) (*T)(i, j) = H(i, j);
-    if (!schur(*T, *Z)) {
-      set_error("QR iteration on the projected matrix did not converge");
-      return FQ_ENUMERIC;
-    }
-    schur_sort(*T, *Z, std::min(nsort, mm), [](const zd& a, const zd& b) { return std::abs(a) > std::abs(b); });
-    bz->assign(mm, zd(0, 0));
-    for (int c = 0; c < mm; ++c) {
-      zd acc = 0;
-      for (int i = 0; i < mm; ++i) acc += H(mm, i) * (*Z)(i, c);
-      (*bz)[c] = acc;
-    }
-    *nconv = 0;
-    *worst = 0.0;
-    *X = ZMat(mm, nev);
-    for (int i = 0; i < nev; ++i) {
-      std::vector<zd> y = tri_eigvec(*T, i);
-      double yn = 0.0;
-      for (const zd& v : y) yn += std::norm(v);
-      yn = std::sqrt(yn);
-      zd e = 0;
-      for (int l = 0; l <= i; ++l) e += (*bz)[l] * y[l];
-      const double est = std::abs(e) / (yn * std::max(std::abs((*T)(i, i)), 1e-300));
-      *worst = std::max(*worst, est);
-      if (est <= tolg) ++*nconv;
-      for (int r = 0; r < mm; ++r) {
-        zd acc = 0;
-        for (int l = 0; l <= i; ++l) acc += (*Z)(r, l) * y[l];
-        (*X)(r, i) = acc / yn;
-      }
-    }
+    const fq_status st = analyse_decomposition(H, mm, nsort, nev, tolg, T, Z, bz, X, nconv, worst);
     t_restart += now_s() - t2;
-    return FQ_OK;
+    return st;
   }
 };
 
-fq_status validate(const floquet_op* op, int nev, const fq_arnoldi_opts* o) {
+}  // namespace
+
+fq_status validate_arnoldi(const floquet_op* op, int nev, const fq_arnoldi_opts* o) {
   if (!op) {
     set_error("op is NULL");
     return FQ_EINVAL;
@@ -420,8 +444,6 @@ fq_status validate(const floquet_op* op, int nev, const fq_arnoldi_opts* o) {
   return FQ_OK;
 }
 
-}  // namespace
-
 fq_status poly_scale_copy(floquet_op* op, zd a, fq_dtype dt, const void* psi, void* out, hipStream_t s) {
   if (dt == FQ_C64)
     FQ_HIP_CHECK(launch_scale_c64(static_cast<const c64*>(psi), a.real(), a.imag(), static_cast<c64*>(out), op->dim(), s));
@@ -433,7 +455,7 @@ fq_status poly_scale_copy(floquet_op* op, zd a, fq_dtype dt, const void* psi, vo
 
 fq_status arnoldi_solve(floquet_op* op, int nev, double phi, const fq_arnoldi_opts* o, double* evals_host,
                         void* evecs_dev, double* resid_host, fq_arnoldi_stats* stats, hipStream_t s) {
-  FQ_TRY(validate(op, nev, o));
+  FQ_TRY(validate_arnoldi(op, nev, o));
   const double t_start = now_s();
   fq_arnoldi_stats local{};
   fq_arnoldi_stats* st = stats ? stats : &local;
@@ -485,15 +507,8 @@ fq_status arnoldi_solve(floquet_op* op, int nev, double phi, const fq_arnoldi_op
     if (o->refine && rmax > o->tol) {
       const double t_ref0 = now_s();
       // warm start: v0 = sum_i c_i y_i over the complex64 Ritz vectors
-      std::vector<c128> cc(static_cast<size_t>(nev));
-      uint64_t x = o->seed * 0x9E3779B97F4A7C15ull + 12345;
-      for (int i = 0; i < nev; ++i) {
-        x ^= x << 13;
-        x ^= x >> 7;
-        x ^= x << 17;
-        const double ang = double(x >> 11) * (2.0 * M_PI / 9007199254740992.0);
-        cc[i] = mk<double>(std::cos(ang), std::sin(ang));
-      }
+      std::vector<c128> cc;
+      warm_start_coefs(o->seed, nev, &cc);
       FQ_HIP_CHECK(hipMemcpyAsync(sv.ws.qbuf, cc.data(), cc.size() * sizeof(c128), hipMemcpyHostToDevice, s));
       FQ_HIP_CHECK(launch_basis_gemm(sv.ws.ritz, d, nev, sv.ws.qbuf, 1, sv.ws.V, d, d, s));
       FQ_TRY(normalize_col(sv.ws, 0, &n0, s));
@@ -570,28 +585,12 @@ fq_status arnoldi_eigs(floquet_op* op, int nev, double phi, const fq_arnoldi_opt
 }
 
 fq_status arnoldi_eigs_batched(floquet_op* const* ops, int n_ops, const double* phis, int n_phi, int nev,
-                               const fq_arnoldi_opts* opts, double* evals_host, void* const* evecs_dev,
-                               double* resid_host, fq_arnoldi_stats* stats, void* hip_stream) {
+                               const fq_arnoldi_opts* opts, const int* k_per_op, double* evals_host,
+                               void* const* evecs_dev, double* resid_host, fq_arnoldi_stats* stats,
+                               void* hip_stream) {
   clear_error();
-  if (!ops || n_ops < 1 || !phis || n_phi < 1 || !evals_host) {
-    set_error("arnoldi_eigs_batched: need ops, n_ops >= 1, phis, n_phi >= 1 and evals_host");
-    return FQ_EINVAL;
-  }
-  fq_status worst = FQ_OK;
-  std::string first_err;
-  for (int i = 0; i < n_ops; ++i) {
-    for (int j = 0; j < n_phi; ++j) {
-      const size_t pidx = size_t(i) * n_phi + j;
-      fq_status st = arnoldi_solve(ops[i], nev, phis[j], opts, evals_host + 2 * nev * pidx,
-                                   evecs_dev ? evecs_dev[pidx] : nullptr, resid_host ? resid_host + nev * pidx : nullptr,
-                                   stats ? stats + pidx : nullptr, static_cast<hipStream_t>(hip_stream));
-      if (st != FQ_OK && first_err.empty()) first_err = floquet_last_error();
-      if (st < 0 && (worst >= 0 || st < worst)) worst = st;
-      if (st == FQ_NOT_CONVERGED && worst == FQ_OK) worst = st;
-    }
-  }
-  if (!first_err.empty()) set_error(first_err);
-  return worst;
+  return arnoldi_batched_solve(ops, n_ops, phis, n_phi, nev, opts, k_per_op, evals_host, evecs_dev, resid_host, stats,
+                               static_cast<hipStream_t>(hip_stream));
 }
 
 fq_status fq_paper_parameters(int L, int nev, int* ncv_out, int* k_out) {

@@ -1,0 +1,40 @@
+// Pieces of the Krylov-Schur driver shared by the single-problem solver
+// (krylov.cpp) and the lockstep batched solver (batched.cpp).
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+#include "dense.h"
+
+struct floquet_op;
+
+namespace fq {
+
+// Schur form of S = H[0:mm, 0:mm] with the nsort largest |theta| first, the
+// coupling b^T Z of the residual row, the Ritz coefficient vectors X (mm x nev)
+// and the relative Ritz estimates of the nev wanted pairs (nconv of them
+// below tolg, the largest in worst).  Host only; thread-safe.
+fq_status analyse_decomposition(const ZMat& H, int mm, int nsort, int nev, double tolg, ZMat* T, ZMat* Z,
+                                std::vector<zd>* bz, ZMat* X, int* nconv, double* worst);
+
+// Argument checks shared by arnoldi_eigs and arnoldi_eigs_batched.
+fq_status validate_arnoldi(const floquet_op* op, int nev, const fq_arnoldi_opts* o);
+
+// Schur vectors kept at a restart: p = nev + (m - nev) / 2, within [nev + 1, m - 1].
+int keep_count(int m, int nev);
+
+// Unit-modulus coefficients of the FP64 warm start v0 = sum_i c_i y_i.
+void warm_start_coefs(unsigned long long seed, int nev, std::vector<c128>* cc);
+
+// Single-problem solve (arnoldi_eigs).
+fq_status arnoldi_solve(floquet_op* op, int nev, double phi, const fq_arnoldi_opts* o, double* evals_host,
+                        void* evecs_dev, double* resid_host, fq_arnoldi_stats* stats, hipStream_t s);
+
+// Lockstep batched solve (arnoldi_eigs_batched); k_per_op may be NULL.
+fq_status arnoldi_batched_solve(floquet_op* const* ops, int n_ops, const double* phis, int n_phi, int nev,
+                                const fq_arnoldi_opts* o, const int* k_per_op, double* evals_host,
+                                void* const* evecs_dev, double* resid_host, fq_arnoldi_stats* stats,
+                                hipStream_t s);
+
+}  // namespace fq

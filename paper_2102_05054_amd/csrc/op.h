@@ -39,6 +39,14 @@ struct KiPlan {
 // Brickwork: per-pass gate program (see bw_kernels.h).
 struct BwProgram;
 
+// Kicked-Ising tile plans (floquet_api.cpp).
+void tile_shape(int n, int* rb, int* tb);
+void pass_shape(int n, unsigned ntiles, int* rb, int* tb);
+KickMasks masks_for(unsigned kbits, int n, int rb, int tb);
+void single_shape(int L, int* rb, int* tb);
+KiPlan make_plan(int L, bool c64_dt);
+bool single_ok(int L, bool c64_dt);
+
 }  // namespace fq
 
 struct floquet_op {

@@ -21,7 +21,7 @@ import sys
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ["csrc/ki_kernels.hip", "csrc/tile_engine.h", "csrc/ki_kernels.h"]
+KERNEL_SOURCES = ["csrc/ki_kernels_impl.h", "csrc/tile_engine.h", "csrc/ki_kernels.h"]
 
 
 def kernel_hash() -> str:

@@ -1,0 +1,140 @@
+"""GPU parity of the lockstep batched eigensolver (many disorder
+realisations, targets phi and chain lengths in one call) against full
+diagonalisation, the oracle's matrix-free U and the single-problem solver."""
+
+import math
+
+import numpy as np
+import pytest
+
+from gpu_util import bw_op, ki_op, require_gpu, say, to_np
+from oracle import eig, models
+from workloads import brickwork, kicked_ising
+
+pytestmark = pytest.mark.gpu
+
+
+def _batched(ops, phis, nev, **kw):
+    from paper_2102_05054_amd import arnoldi_eigs_batched
+    return arnoldi_eigs_batched(ops, phis, nev, **kw)
+
+
+def _paper_k(L, ncv, lo=8):
+    return max(lo, int(0.8 * 2 ** (L + 1) / ncv))
+
+
+@pytest.mark.parametrize("filter_dtype", ["c64", "c128"])
+def test_batched_against_dense(filter_dtype):
+    # sizes 6..10 (three buckets, two realisations sharing one), three targets
+    require_gpu()
+    specs = [(6, 0), (8, 0), (8, 1), (10, 0), (10, 1)]
+    params = [kicked_ising(L, 700 + 10 * L + r) for L, r in specs]
+    phis = [0.0, 1.3, math.pi]
+    nev, ncv = 6, 24
+    ks = [_paper_k(p.L, ncv) for p in params]
+    say(f"batched vs dense {filter_dtype}: sizes {[p.L for p in params]}, k {ks}")
+    ops = [ki_op(p) for p in params]
+    try:
+        ev, res, stats, st, vecs = _batched(ops, phis, nev, k=ks, ncv=ncv, tol=1e-10, filter_dtype=filter_dtype,
+                                            seed=2, want_vectors=True)
+        for i, p in enumerate(params):
+            U = models.ki_dense(p)
+            for j, phi in enumerate(phis):
+                om_ref, _ = eig.full_closest(U, nev, phi)
+                err = np.max(np.abs(ev[i, j] - om_ref))
+                assert err < 1e-12, (p.L, phi, err)
+                assert res[i, j].max() <= 1e-10
+                s = stats[i * len(phis) + j]
+                assert s["nconv"] == nev
+                assert s["n_U_apps"] > 0
+                if filter_dtype == "c64":
+                    assert s["n_U_apps_c64"] > 0
+                V = to_np(vecs[i * len(phis) + j])
+                for n in range(nev):
+                    assert abs(np.linalg.norm(V[n]) - 1) < 1e-12
+                    assert np.linalg.norm(U @ V[n] - ev[i, j, n] * V[n]) < 1e-10
+    finally:
+        for o in ops:
+            o.close()
+
+
+def test_batched_matches_single_solver():
+    # larger chains (matrix-free oracle residuals) and the same answers as the
+    # one-problem-at-a-time solver
+    require_gpu()
+    specs = [(12, 0), (12, 1), (13, 0), (14, 0)]
+    params = [kicked_ising(L, 4100 + 10 * L + r) for L, r in specs]
+    phis = [0.0, 0.5 * math.pi]
+    nev, ncv = 10, 40
+    ks = [_paper_k(p.L, ncv) for p in params]
+    say(f"batched vs single: sizes {[p.L for p in params]}, k {ks}")
+    ops = [ki_op(p) for p in params]
+    try:
+        ev, res, stats, st, vecs = _batched(ops, phis, nev, k=ks, ncv=ncv, tol=1e-10, filter_dtype="c64",
+                                            seed=5, want_vectors=True)
+        for i, p in enumerate(params):
+            mv = models.matvec(p)
+            for j, phi in enumerate(phis):
+                assert res[i, j].max() <= 1e-10
+                V = to_np(vecs[i * len(phis) + j])
+                r_or = eig.residuals(mv, ev[i, j], V.T)
+                assert r_or.max() < 1e-10, (p.L, phi, r_or.max())
+                assert np.max(np.abs(np.abs(ev[i, j]) - 1)) < 1e-10
+                ev1, _, res1, st1, _ = ops[i].arnoldi_eigs(nev, phi, k=ks[i], ncv=ncv, tol=1e-10, filter_dtype="c64",
+                                                           seed=5, want_vectors=False)
+                assert np.max(np.abs(np.sort_complex(ev1) - np.sort_complex(ev[i, j]))) < 1e-12
+                say(f"L={p.L} phi={phi:.3f}: restarts batched {stats[i * len(phis) + j]['n_restarts']}"
+                    f" single {st1['n_restarts']}")
+    finally:
+        for o in ops:
+            o.close()
+
+
+def test_batched_mixed_models_fall_back():
+    # brickwork goes through the one-by-one path inside the call
+    require_gpu()
+    pk = kicked_ising(8, 31)
+    pb = brickwork(8, 33)
+    ops = [ki_op(pk), bw_op(pb)]
+    try:
+        ev, res, stats, st = _batched(ops, [0.4, 2.0], 4, k=[17, 17], ncv=24, tol=1e-10, filter_dtype="c64")
+        for i, p in enumerate([pk, pb]):
+            for j, phi in enumerate([0.4, 2.0]):
+                om_ref, _ = eig.full_closest(models.dense(p), 4, phi)
+                assert np.max(np.abs(ev[i, j] - om_ref)) < 1e-12, (i, j)
+                assert res[i, j].max() <= 1e-10
+    finally:
+        for o in ops:
+            o.close()
+
+
+def test_batched_tiny_chains():
+    # L = 3 is solved one by one, L = 4 in a batch of its own (16 amplitudes)
+    require_gpu()
+    params = [kicked_ising(3, 51), kicked_ising(4, 52), kicked_ising(4, 53)]
+    ops = [ki_op(p) for p in params]
+    try:
+        ev, res, stats, st = _batched(ops, [0.0, 3.0], 2, k=[3, 4, 4], ncv=6, tol=1e-10, filter_dtype="c128")
+        for i, p in enumerate(params):
+            for j, phi in enumerate([0.0, 3.0]):
+                om_ref, _ = eig.full_closest(models.dense(p), 2, phi)
+                assert np.max(np.abs(ev[i, j] - om_ref)) < 1e-12, (i, j)
+                assert res[i, j].max() <= 1e-10
+    finally:
+        for o in ops:
+            o.close()
+
+
+def test_batched_argument_errors():
+    require_gpu()
+    from paper_2102_05054_amd import FloquetError
+    op = ki_op(kicked_ising(8, 40))
+    try:
+        with pytest.raises(FloquetError):
+            _batched([op], [0.0], 4, k=[0], ncv=12)
+        with pytest.raises(FloquetError):
+            _batched([op], [float("nan")], 4, k=10, ncv=12)
+        with pytest.raises(FloquetError):
+            _batched([op], [0.0], 4, k=10, ncv=5)
+    finally:
+        op.close()
