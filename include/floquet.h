@@ -124,6 +124,7 @@ typedef struct {
   int refine;              /* with FQ_C64: finish in FP64 until tol is met */
   unsigned long long seed; /* start vector seed when v0_dev is NULL */
   const void* v0_dev;      /* optional complex128 start vector (d), or NULL */
+  int refine_k;            /* filter order of the FP64 refinement (0: k) */
 } fq_arnoldi_opts;
 
 /* Counters and per-phase wall times (seconds) of one solve. */

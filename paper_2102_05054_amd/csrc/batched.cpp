@@ -94,6 +94,7 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Bucket {
   int L = 0, k = 0;
+  int k_ref = 0;  // filter order of the FP64 refinement
   bool sw = false;
   std::vector<Prob> P;
   size_t d = 0;
@@ -338,7 +339,7 @@ fq_status step(Bucket& B, const std::vector<Seg>& segs) {
       FQ_TRY(ki_batch_filter<float>(B.sh32, B.k, B.f32, B.list + pos0, n, B.s));
       FQ_HIP_CHECK(launch_b_cast_out(B.args(B.list + pos0, n), B.f32, B.s));
     } else {
-      FQ_TRY(ki_batch_filter<double>(B.sh64, B.k, B.f64, B.list + pos0, n, B.s));
+      FQ_TRY(ki_batch_filter<double>(B.sh64, B.mixed ? B.k_ref : B.k, B.f64, B.list + pos0, n, B.s));
     }
   }
   for (const Seg& g : segs) {
@@ -595,7 +596,7 @@ fq_status start_refine(Bucket& B, const std::vector<int>& W) {
     p.t_ref0 = now_s();
   }
   if (!B.have64) {
-    FQ_TRY(ki_batch_tune<double>(B.L, B.sw, B.k, B.f64, B.aux, n, B.s, &B.sh64, nullptr));
+    FQ_TRY(ki_batch_tune<double>(B.L, B.sw, B.k_ref, B.f64, B.aux, n, B.s, &B.sh64, nullptr));
     B.have64 = true;
   }
   return FQ_OK;
@@ -692,11 +693,12 @@ fq_status run_bucket(Bucket& B, const Out& out) {
   // single-problem solver), normalised
   for (int qi = 0; qi < np; ++qi) FQ_HIP_CHECK(launch_random(B.P[qi].V, B.d, B.o->seed, B.s));
   FQ_HIP_CHECK(launch_b_normalize_col(B.args(B.ident, np), 0, B.s));
+  const bool probes = probes_pay(B.d, B.k, B.P.size());
   for (Prob& p : B.P) {
     if (B.mixed)
-      fresh_phase(B, p, Ph::C64, false, false, std::max(B.o->tol, 2e-6), B.o->max_restarts);
+      fresh_phase(B, p, Ph::C64, false, probes, std::max(B.o->tol, 2e-6), B.o->max_restarts);
     else
-      fresh_phase(B, p, Ph::C128, true, false, 0.5 * B.o->tol, B.o->max_restarts);
+      fresh_phase(B, p, Ph::C128, true, probes, 0.5 * B.o->tol, B.o->max_restarts);
     p.t_filter0 = 0.0;
     p.t_restart0 = 0.0;
   }
@@ -741,8 +743,12 @@ fq_status run_bucket(Bucket& B, const Out& out) {
       Prob& p = B.P[kq.second];
       ++p.j;
       p.st.n_filter_apps += 1;
-      p.st.n_U_apps += B.k;
-      if (p.ph == Ph::C64) p.st.n_U_apps_c64 += B.k;
+      if (p.ph == Ph::C64) {
+        p.st.n_U_apps += B.k;
+        p.st.n_U_apps_c64 += B.k;
+      } else {
+        p.st.n_U_apps += B.mixed ? B.k_ref : B.k;
+      }
     }
     // decisions synchronise; time the steps up to there
     bool any = false;
@@ -866,6 +872,7 @@ fq_status arnoldi_batched_solve(floquet_op* const* ops, int n_ops, const double*
         B.L = L;
         B.sw = std::get<1>(kv.first);
         B.k = std::get<2>(kv.first);
+        B.k_ref = o->refine_k > 0 ? o->refine_k : B.k;
         B.d = d;
         B.nblk = nblk;
         B.ncv = ncv;

@@ -2,6 +2,8 @@
 #include "ki_batched.h"
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <string>
@@ -63,6 +65,9 @@ fq_status bpass(const KiBatchShape& sh, const KiGroup& g, const KiDesc<Real>* de
   a.desc = desc;
   a.list = list;
   a.from_psi = from_psi;
+  a.flat = sh.flat ? 1 : 0;
+  a.tile_log = 0;
+  while ((1u << a.tile_log) < g.ntiles) ++a.tile_log;
   const hipError_t e = ki_launch_pass<Real>(a, g.rb, g.tb, sh.sw, g.ntiles, s, n);
   if (e != hipSuccess) return launch_err("batched kicked-Ising pass launch failed", e);
   return FQ_OK;
@@ -148,6 +153,15 @@ fq_status ki_batch_filter(const KiBatchShape& sh, int k, const KiDesc<Real>* des
     return FQ_EINVAL;
   }
   if (sh.single) return bsingle<Real>(sh, desc, list, n, k, KI_ADD_PSI, s);
+  if (sh.chunk > 0 && n > sh.chunk) {
+    KiBatchShape one = sh;
+    one.chunk = 0;
+    for (unsigned c0 = 0; c0 < n; c0 += sh.chunk) {
+      const fq_status st = ki_batch_filter<Real>(one, k, desc, list + c0, std::min(sh.chunk, n - c0), s);
+      if (st != FQ_OK) return st;
+    }
+    return FQ_OK;
+  }
   const KiPlan& pl = sh.plan;
   if (!plan_ok(pl, sh.L)) {
     set_error("internal: inconsistent batched kicked-Ising tile plan");
@@ -197,6 +211,15 @@ namespace {
 std::mutex g_tune_mu;
 std::map<std::tuple<int, bool, bool, int, int>, KiBatchShape> g_tuned;
 
+// FQ_VERBOSE=1 prints the tuner's choice to stderr.
+bool tune_verbose() {
+  static const bool v = [] {
+    const char* e = std::getenv("FQ_VERBOSE");
+    return e && e[0] && e[0] != '0';
+  }();
+  return v;
+}
+
 int size_class(unsigned n) {
   int c = 0;
   while ((1u << c) < n) ++c;
@@ -223,45 +246,67 @@ fq_status ki_batch_tune(int L, bool sw, int k, const KiDesc<Real>* desc, const i
     set_error("no kicked-Ising tile shape for L = " + std::to_string(L));
     return FQ_EINVAL;
   }
-  int best = 0;
+  const int kt = std::min(k, 32);
+  hipEvent_t e0, e1;
+  FQ_HIP_CHECK(hipEventCreate(&e0));
+  FQ_HIP_CHECK(hipEventCreate(&e1));
+  // time per Horner step of one candidate (negative: could not be launched)
+  auto time_one = [&](const KiBatchShape& c) -> double {
+    if (ki_batch_filter<Real>(c, kt, desc, list, n, s) != FQ_OK) {
+      (void)hipGetLastError();
+      return -1.0;
+    }
+    (void)hipEventRecord(e0, s);
+    bool ok = true;
+    for (int r = 0; r < 2 && ok; ++r) ok = ki_batch_filter<Real>(c, kt, desc, list, n, s) == FQ_OK;
+    (void)hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess || !ok) {
+      (void)hipGetLastError();
+      return -1.0;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    return 1000.0 * ms / (2.0 * kt);
+  };
+  KiBatchShape best = cands[0];
   double best_t = -1.0;
-  if (cands.size() > 1) {
-    const int kt = std::min(k, 32);
-    hipEvent_t e0, e1;
-    FQ_HIP_CHECK(hipEventCreate(&e0));
-    FQ_HIP_CHECK(hipEventCreate(&e1));
-    for (size_t c = 0; c < cands.size(); ++c) {
-      if (ki_batch_filter<Real>(cands[c], kt, desc, list, n, s) != FQ_OK) {
-        (void)hipGetLastError();
-        continue;
-      }
-      (void)hipEventRecord(e0, s);
-      bool ok = true;
-      for (int r = 0; r < 2 && ok; ++r) ok = ki_batch_filter<Real>(cands[c], kt, desc, list, n, s) == FQ_OK;
-      (void)hipEventRecord(e1, s);
-      if (hipEventSynchronize(e1) != hipSuccess || !ok) {
-        (void)hipGetLastError();
-        continue;
-      }
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      const double us = 1000.0 * ms / (2.0 * kt);
-      if (best_t < 0.0 || us < best_t) {
-        best_t = us;
-        best = static_cast<int>(c);
-      }
+  auto consider = [&](const KiBatchShape& c) {
+    const double us = time_one(c);
+    if (us >= 0.0 && (best_t < 0.0 || us < best_t)) {
+      best_t = us;
+      best = c;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (best_t < 0.0) {
-      set_error("no kicked-Ising tile shape could be launched for L = " + std::to_string(L));
-      return FQ_EDEVICE;
+  };
+  // stage 1: tile shapes
+  for (const KiBatchShape& c : cands) consider(c);
+  // stage 2: sub-batch size, stage 3: XCD mapping (multi-pass shapes)
+  if (best_t >= 0.0 && !best.single) {
+    const KiBatchShape base = best;
+    for (unsigned ch : {256u, 128u, 64u, 32u, 16u}) {
+      if (ch >= n) continue;
+      KiBatchShape c = base;
+      c.chunk = ch;
+      consider(c);
     }
+    KiBatchShape c = best;
+    c.flat = true;
+    consider(c);
   }
-  *out = cands[best];
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (best_t < 0.0) {
+    set_error("no kicked-Ising tile shape could be launched for L = " + std::to_string(L));
+    return FQ_EDEVICE;
+  }
+  if (tune_verbose())
+    std::fprintf(stderr, "[fq] tuned L=%d %s n=%u k=%d: %s rb/tb %d/%d chunk %u flat %d: %.2f us/step\n", L,
+                 c64_dt ? "c64" : "c128", n, k, best.single ? "single" : "multi-pass",
+                 best.single ? best.srb : best.plan.grp[0].rb, best.single ? best.stb : best.plan.grp[0].tb,
+                 best.chunk, best.flat ? 1 : 0, best_t);
+  *out = best;
   if (best_us) *best_us = best_t;
   std::lock_guard<std::mutex> g(g_tune_mu);
-  g_tuned[key] = cands[best];
+  g_tuned[key] = best;
   return FQ_OK;
 }
 

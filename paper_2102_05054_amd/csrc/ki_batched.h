@@ -18,6 +18,11 @@ struct KiBatchShape {
   bool single = false;
   int srb = 0, stb = 0;  // single-workgroup tile
   KiPlan plan;           // multi-pass plan
+  // multi-pass only: run the k steps on sub-batches of at most `chunk`
+  // problems (0 = all at once), so that a sub-batch's states stay in the
+  // Infinity Cache across passes; `flat` keeps each problem on one XCD
+  unsigned chunk = 0;
+  bool flat = false;
 };
 
 // Candidate shapes for (L, kick form, precision), the default first.
@@ -34,9 +39,10 @@ template <typename Real>
 fq_status ki_batch_apply(const KiBatchShape& sh, const KiDesc<Real>* desc, const int* list, unsigned n,
                          hipStream_t s);
 
-// Autotuner: times every candidate shape on the given problems (their psi and
-// x buffers are overwritten) for min(k, 32) Horner steps and returns the
-// fastest; results are cached per (L, kick form, precision, k, batch size
+// Autotuner: times the candidate shapes on the given problems (their psi and
+// x buffers are overwritten) for min(k, 32) Horner steps, then the sub-batch
+// sizes and the XCD mapping for the fastest shape, and returns the fastest
+// combination; results are cached per (L, kick form, precision, k, batch size
 // class).  best_us (optional) receives the time per Horner step of the batch.
 template <typename Real>
 fq_status ki_batch_tune(int L, bool sw, int k, const KiDesc<Real>* desc, const int* list, unsigned n,

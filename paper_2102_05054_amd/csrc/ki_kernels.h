@@ -46,10 +46,14 @@ struct KiPassArgs {
   int flags;
   KickMasks k1, k2;         // before / after the phase
   // batched launches: problem desc[list[blockIdx.y]]; the pass reads psi
-  // (from_psi) or x and writes x
+  // (from_psi) or x and writes x.  With flat, the grid is one-dimensional
+  // over (problem, tile) pairs, problem-major, dealt to the XCDs in
+  // contiguous runs, so that all tiles of a problem share one L2
+  // (tile_log = log2 of the tiles per problem).
   const KiDesc<Real>* desc;
   const int* list;
   int from_psi;
+  int flat, tile_log;
 };
 
 template <typename Real>

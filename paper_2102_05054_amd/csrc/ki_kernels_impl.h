@@ -127,8 +127,7 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
   extern __shared__ char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
   const int tid = threadIdx.x;
-  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-  const TileMap tm = make_tile_map(tile, a.n, a.c, a.p);
+  uint32_t tile;
   const C* __restrict__ xin;
   C* __restrict__ xout;
   const C* __restrict__ psi;
@@ -136,7 +135,16 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
   const C* __restrict__ thi;
   Real w;
   if constexpr (BATCH) {
-    const KiDesc<Real>& D = a.desc[a.list[blockIdx.y]];
+    uint32_t q;
+    if (a.flat) {
+      const uint32_t idx = xcd_tile(blockIdx.x, gridDim.x);
+      q = idx >> a.tile_log;
+      tile = idx & ((1u << a.tile_log) - 1u);
+    } else {
+      q = blockIdx.y;
+      tile = xcd_tile(blockIdx.x, gridDim.x);
+    }
+    const KiDesc<Real>& D = a.desc[a.list[q]];
     xin = a.from_psi ? D.psi : D.x;
     xout = D.x;
     psi = D.psi;
@@ -144,6 +152,7 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
     thi = D.thi;
     w = static_cast<Real>(D.w);
   } else {
+    tile = xcd_tile(blockIdx.x, gridDim.x);
     xin = a.xin;
     xout = a.xout;
     psi = a.psi;
@@ -151,6 +160,7 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
     thi = a.thi;
     w = static_cast<Real>(a.w);
   }
+  const TileMap tm = make_tile_map(tile, a.n, a.c, a.p);
   const bool do_ph = (a.flags & KI_PHASE) != 0;
   const bool do_ps = (a.flags & KI_ADD_PSI) != 0;
 
@@ -345,7 +355,8 @@ hipError_t launch_pass_t(const KiPassArgs<Real>& a, unsigned ntiles, unsigned np
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(kern, dim3(ntiles, BATCH ? nprob : 1u), dim3(1 << TB), shmem, s, a);
+  const dim3 grid = !BATCH ? dim3(ntiles) : (a.flat ? dim3(ntiles * nprob) : dim3(ntiles, nprob));
+  hipLaunchKernelGGL(kern, grid, dim3(1 << TB), shmem, s, a);
   return hipGetLastError();
 }
 
@@ -383,6 +394,8 @@ hipError_t ki_launch_pass(const KiPassArgs<Real>& a, int rb, int tb, bool sw, un
                           unsigned nprob) {
   const bool pf = (a.flags & KI_PREFETCH_PHASE) != 0;
   if (nprob > 0 && (!a.desc || !a.list || nprob > 65535u)) return hipErrorInvalidValue;
+  if (nprob > 0 && a.flat && (ntiles != (1u << a.tile_log) || size_t(ntiles) * nprob > 0x7fffffffu))
+    return hipErrorInvalidValue;
 #define FQ_CASE4(RB_, TB_, PF_)                                                                    \
   if (nprob > 0)                                                                                   \
     return sw ? launch_pass_t<Real, RB_, TB_, true, PF_, true>(a, ntiles, nprob, s)                \

@@ -40,6 +40,8 @@ namespace fq {
 // Schur form of S = H[0:mm, 0:mm] with the nsort largest |theta| first,
 // b^T Z, and the Ritz coefficient vectors / relative estimates of the nev
 // wanted pairs.
+bool probes_pay(size_t d, int k, size_t nprob) { return double(d) * k * double(nprob) >= 16777216.0; }
+
 int keep_count(int m, int nev) { return std::min(m - 1, std::max(nev + 1, nev + (m - nev) / 2)); }
 
 void warm_start_coefs(unsigned long long seed, int nev, std::vector<c128>* cc) {
@@ -293,7 +295,7 @@ struct Solver {
   // V[:, 0].  Stops when all nev wanted Ritz estimates are below
   // tolg*|theta| and, if check_true, the FP64 residuals are below tol.
   // With `early`, the projected matrix is also analysed every few steps
-  // inside a cycle (a warm start reaches convergence after ~nev steps).
+  // inside a cycle, so that a run can stop before the cycle is full.
   fq_status run(fq_dtype dt, double tolg, double tol, bool check_true, int restart_budget, bool early,
                 PhaseResult* res) {
     const int m = ncv;
@@ -437,8 +439,9 @@ fq_status validate_arnoldi(const floquet_op* op, int nev, const fq_arnoldi_opts*
   }
   const long long d = (long long)op->dim();
   if (nev < 1 || o->ncv < nev + 2 || o->ncv > d || o->k < 0 || !(o->tol > 0) || o->max_restarts < 0 ||
-      (o->filter_dtype != FQ_C64 && o->filter_dtype != FQ_C128) || o->ncv > 3000) {
-    set_error("arnoldi_eigs: need 1 <= nev, nev + 2 <= ncv <= min(d, 3000), k >= 0, tol > 0, max_restarts >= 0");
+      (o->filter_dtype != FQ_C64 && o->filter_dtype != FQ_C128) || o->ncv > 3000 || o->refine_k < 0) {
+    set_error("arnoldi_eigs: need 1 <= nev, nev + 2 <= ncv <= min(d, 3000), k >= 0, refine_k >= 0, tol > 0, "
+              "max_restarts >= 0");
     return FQ_EINVAL;
   }
   return FQ_OK;
@@ -497,11 +500,11 @@ fq_status arnoldi_solve(floquet_op* op, int nev, double phi, const fq_arnoldi_op
   fq_status status = FQ_OK;
   const bool mixed = o->filter_dtype == FQ_C64;
   if (!mixed) {
-    FQ_TRY(sv.run(FQ_C128, 0.5 * o->tol, o->tol, true, o->max_restarts, false, &res));
+    FQ_TRY(sv.run(FQ_C128, 0.5 * o->tol, o->tol, true, o->max_restarts, probes_pay(op->dim(), o->k, 1), &res));
   } else {
     // complex64 phase: converge the Ritz estimates to the c64 level
     const double tol32 = std::max(o->tol, 2e-6);
-    FQ_TRY(sv.run(FQ_C64, tol32, o->tol, false, o->max_restarts, false, &res));
+    FQ_TRY(sv.run(FQ_C64, tol32, o->tol, false, o->max_restarts, probes_pay(op->dim(), o->k, 1), &res));
     double rmax = 0.0;
     for (double r : res.ritz.resid) rmax = std::max(rmax, r);
     if (o->refine && rmax > o->tol) {
@@ -514,6 +517,7 @@ fq_status arnoldi_solve(floquet_op* op, int nev, double phi, const fq_arnoldi_op
       FQ_TRY(normalize_col(sv.ws, 0, &n0, s));
       PhaseResult res2;
       res2.restarts = 0;
+      if (o->refine_k > 0) sv.k = o->refine_k;
       const int budget = std::max(0, o->max_restarts - res.restarts);
       FQ_TRY(sv.run(FQ_C128, 0.5 * o->tol, o->tol, true, budget, true, &res2));
       res2.restarts += res.restarts;

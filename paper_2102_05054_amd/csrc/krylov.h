@@ -21,6 +21,12 @@ fq_status analyse_decomposition(const ZMat& H, int mm, int nsort, int nev, doubl
 // Argument checks shared by arnoldi_eigs and arnoldi_eigs_batched.
 fq_status validate_arnoldi(const floquet_op* op, int nev, const fq_arnoldi_opts* o);
 
+// Whether convergence checks inside a cycle (every max(4, m/16) steps) are
+// worth their host synchronisation and small Schur analysis: when one filter
+// application of the batch costs at least 2^24 amplitude updates.  A warm
+// started FP64 refinement always checks.
+bool probes_pay(size_t d, int k, size_t nprob);
+
 // Schur vectors kept at a restart: p = nev + (m - nev) / 2, within [nev + 1, m - 1].
 int keep_count(int m, int nev);
 

@@ -57,3 +57,19 @@ def test_not_converged_reports_partial():
                                                 want_vectors=False, allow_not_converged=True)
     assert st == 1
     assert stats["nconv"] == int((res <= 1e-10).sum())
+
+
+def test_refinement_filter_order():
+    # a separate (lower) filter order for the FP64 refinement still meets the
+    # FP64 targets; the U-application count reflects both orders
+    p = kicked_ising(10, 77)
+    U = models.ki_dense(p)
+    om_ref, _ = eig.full_closest(U, 8, 0.7)
+    with ki_op(p) as op:
+        ev, _, res, st, status = op.arnoldi_eigs(8, 0.7, k=40, ncv=24, tol=1e-10, filter_dtype="c64", seed=4,
+                                                 want_vectors=False, refine_k=20)
+    assert np.max(np.abs(ev - om_ref)) < 1e-12
+    assert res.max() <= 1e-10
+    assert st["n_U_apps_c64"] % 40 == 0
+    # FP64 part: refinement filter applications of order 20 plus nev = 8 U per Ritz check
+    assert st["n_U_apps"] > st["n_U_apps_c64"]

@@ -138,3 +138,18 @@ def test_batched_argument_errors():
             _batched([op], [0.0], 4, k=10, ncv=5)
     finally:
         op.close()
+
+
+def test_batched_refinement_filter_order():
+    require_gpu()
+    params = [kicked_ising(9, 61), kicked_ising(9, 62)]
+    ops = [ki_op(p) for p in params]
+    try:
+        ev, res, stats, st = _batched(ops, [0.2], 5, k=30, ncv=20, tol=1e-10, filter_dtype="c64", refine_k=15)
+        for i, p in enumerate(params):
+            om_ref, _ = eig.full_closest(models.dense(p), 5, 0.2)
+            assert np.max(np.abs(ev[i, 0] - om_ref)) < 1e-12
+            assert res[i, 0].max() <= 1e-10
+    finally:
+        for o in ops:
+            o.close()
