@@ -11,21 +11,23 @@ enum : int {
   BW_PSI_COEF = 4,
 };
 
-// One window: up to four gates of one layer inside tile bits [b, b + wb).
+// One window: up to three gates of one layer inside tile bits [b, b + wb).
 // kind 2 = two-site gate on local bits (l, l+1), local index 2*b_{l+1} + b_l;
 // kind 1 = one-site gate on local bit l.  mat indexes 16-entry matrices.
 struct BwWindow {
   int8_t b, ngates;
-  int8_t kind[4];
-  int8_t l[4];
-  int16_t mat[4];
+  int8_t kind[3];
+  int8_t l[3];
+  int16_t mat[3];
+  int16_t pad;
 };
+static_assert(sizeof(BwWindow) == 16, "BwWindow is read as one 16-byte word");
 
 struct BwPassArgs {
   const void* xin;
   void* xout;
   const void* psi;
-  const c128* mats;
+  const void* mats;  // 16-entry matrices in the pass precision
   const BwWindow* wins;
   int nwin;
   int n, c, p;

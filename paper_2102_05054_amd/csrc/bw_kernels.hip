@@ -27,73 +27,98 @@ namespace fq {
 
 namespace {
 
-constexpr int BW_TB = 8;  // 256 threads
-constexpr int BW_T = 1 << BW_TB;
-
 __device__ __forceinline__ int bw_phys(int j) { return j + (j >> 4); }
 
 // 4x4 gate on local bits (L0, L0+1) of a window of WB bits
 template <typename Real, int WB, int L0>
-__device__ __forceinline__ void gate2(cpx<Real> (&v)[1 << WB], const c128* __restrict__ M) {
-  cpx<Real> m[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) m[i] = mk<Real>(static_cast<Real>(M[i].x), static_cast<Real>(M[i].y));
+__device__ __forceinline__ void gate2(cpx<Real> (&v)[1 << WB], const cpx<Real> (&m)[16]) {
   constexpr int lo = 1 << L0, hi = 1 << (L0 + 1);
 #pragma unroll
   for (int base = 0; base < (1 << WB); ++base) {
     if (base & (lo | hi)) continue;
     const int idx[4] = {base, base | lo, base | hi, base | hi | lo};  // local index 2*b_hi + b_lo
-    cpx<Real> a[4];
+    cpx<Real> x[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) a[c] = v[idx[c]];
+    for (int c = 0; c < 4; ++c) x[c] = v[idx[c]];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      cpx<Real> acc = cmul(m[4 * r], a[0]);
+      cpx<Real> acc = cmul(m[4 * r], x[0]);
 #pragma unroll
-      for (int c = 1; c < 4; ++c) acc = cfma(m[4 * r + c], a[c], acc);
+      for (int c = 1; c < 4; ++c) acc = cfma(m[4 * r + c], x[c], acc);
       v[idx[r]] = acc;
     }
   }
 }
 
 template <typename Real, int WB, int L0>
-__device__ __forceinline__ void gate1(cpx<Real> (&v)[1 << WB], const c128* __restrict__ M) {
-  const cpx<Real> m00 = mk<Real>(static_cast<Real>(M[0].x), static_cast<Real>(M[0].y));
-  const cpx<Real> m01 = mk<Real>(static_cast<Real>(M[1].x), static_cast<Real>(M[1].y));
-  const cpx<Real> m10 = mk<Real>(static_cast<Real>(M[2].x), static_cast<Real>(M[2].y));
-  const cpx<Real> m11 = mk<Real>(static_cast<Real>(M[3].x), static_cast<Real>(M[3].y));
+__device__ __forceinline__ void gate1(cpx<Real> (&v)[1 << WB], const cpx<Real> (&m)[16]) {
   constexpr int bit = 1 << L0;
 #pragma unroll
   for (int base = 0; base < (1 << WB); ++base) {
     if (base & bit) continue;
-    const cpx<Real> a = v[base], b = v[base | bit];
-    v[base] = cfma(m01, b, cmul(m00, a));
-    v[base | bit] = cfma(m11, b, cmul(m10, a));
+    const cpx<Real> x = v[base], y = v[base | bit];
+    v[base] = cfma(m[1], y, cmul(m[0], x));
+    v[base | bit] = cfma(m[3], y, cmul(m[2], x));
   }
 }
 
 template <typename Real, int WB>
-__device__ __forceinline__ void apply_gate(cpx<Real> (&v)[1 << WB], int kind, int l, const c128* M) {
+__device__ __forceinline__ void apply_gate(cpx<Real> (&v)[1 << WB], int kind, int l, const cpx<Real> (&m)[16]) {
   // kind 2: two-site gate on local bits (l, l+1); kind 1: one-site gate on l
   if (kind == 2) {
-    if (l == 0) gate2<Real, WB, 0>(v, M);
+    if (l == 0) gate2<Real, WB, 0>(v, m);
     if constexpr (WB >= 3)
-      if (l == 1) gate2<Real, WB, 1>(v, M);
+      if (l == 1) gate2<Real, WB, 1>(v, m);
     if constexpr (WB >= 4)
-      if (l == 2) gate2<Real, WB, 2>(v, M);
+      if (l == 2) gate2<Real, WB, 2>(v, m);
   } else {
-    if (l == 0) gate1<Real, WB, 0>(v, M);
-    if (l == 1) gate1<Real, WB, 1>(v, M);
+    if (l == 0) gate1<Real, WB, 0>(v, m);
+    if (l == 1) gate1<Real, WB, 1>(v, m);
     if constexpr (WB >= 3)
-      if (l == 2) gate1<Real, WB, 2>(v, M);
+      if (l == 2) gate1<Real, WB, 2>(v, m);
     if constexpr (WB >= 4)
-      if (l == 3) gate1<Real, WB, 3>(v, M);
+      if (l == 3) gate1<Real, WB, 3>(v, m);
   }
 }
 
-template <typename Real, int WB>
-__global__ void __launch_bounds__(BW_T) bw_pass_kernel(BwPassArgs a) {
+// A window's fields, made wave-uniform (scalar registers) so that the gate
+// dispatch branches on scalars and the matrices can be read with scalar loads.
+struct WinU {
+  int b, ngates;
+  int kind[3], l[3], mat[3];
+};
+
+__device__ __forceinline__ WinU load_window(const BwWindow* p) {
+  const int4 raw = *reinterpret_cast<const int4*>(p);
+  const int x = __builtin_amdgcn_readfirstlane(raw.x);
+  const int y = __builtin_amdgcn_readfirstlane(raw.y);
+  const int z = __builtin_amdgcn_readfirstlane(raw.z);
+  const int t = __builtin_amdgcn_readfirstlane(raw.w);
+  WinU w;
+  w.b = x & 0xff;
+  w.ngates = (x >> 8) & 0xff;
+  w.kind[0] = (x >> 16) & 0xff;
+  w.kind[1] = (x >> 24) & 0xff;
+  w.kind[2] = y & 0xff;
+  w.l[0] = (y >> 8) & 0xff;
+  w.l[1] = (y >> 16) & 0xff;
+  w.l[2] = (y >> 24) & 0xff;
+  w.mat[0] = z & 0xffff;
+  w.mat[1] = (z >> 16) & 0xffff;
+  w.mat[2] = t & 0xffff;
+  return w;
+}
+
+template <typename Real>
+__device__ __forceinline__ void load_mat(cpx<Real> (&m)[16], const cpx<Real>* __restrict__ mats, int idx) {
+#pragma unroll
+  for (int i = 0; i < 16; ++i) m[i] = mats[16 * idx + i];
+}
+
+template <typename Real, int WB, int TB>
+__global__ void __launch_bounds__(1 << TB) bw_pass_kernel(BwPassArgs a) {
   using C = cpx<Real>;
+  constexpr int T = 1 << TB;
   extern __shared__ char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
   const int tid = threadIdx.x;
@@ -102,29 +127,36 @@ __global__ void __launch_bounds__(BW_T) bw_pass_kernel(BwPassArgs a) {
   const TileMap tm = make_tile_map(tile, a.n, a.c, a.p);
   const C* __restrict__ xin = static_cast<const C*>(a.xin);
   C* __restrict__ xout = static_cast<C*>(a.xout);
-  for (int j = tid; j < N; j += BW_T) lds[bw_phys(j)] = xin[tm.g(j)];
+  const C* __restrict__ mats = static_cast<const C*>(a.mats);
+  for (int j = tid; j < N; j += T) lds[bw_phys(j)] = xin[tm.g(j)];
   __syncthreads();
   const int ngroups = N >> WB;
   for (int wi = 0; wi < a.nwin; ++wi) {
-    const BwWindow w = a.wins[wi];
-    const int b = w.b;
-    const uint32_t below = (1u << b) - 1u;
-    for (int g = tid; g < ngroups; g += BW_T) {
+    const WinU w = load_window(a.wins + wi);
+    // the window's matrices, read once per window (uniform addresses)
+    C m0[16], m1[16], m2[16];
+    load_mat<Real>(m0, mats, w.mat[0]);
+    if (w.ngates > 1) load_mat<Real>(m1, mats, w.mat[1]);
+    if (w.ngates > 2) load_mat<Real>(m2, mats, w.mat[2]);
+    const uint32_t below = (1u << w.b) - 1u;
+    for (int g = tid; g < ngroups; g += T) {
       // insert WB zero bits at position b
-      const int base = static_cast<int>((uint32_t(g) & below) | ((uint32_t(g) >> b) << (b + WB)));
+      const int base = static_cast<int>((uint32_t(g) & below) | ((uint32_t(g) >> w.b) << (w.b + WB)));
       C v[1 << WB];
 #pragma unroll
-      for (int m = 0; m < (1 << WB); ++m) v[m] = lds[bw_phys(base + (m << b))];
-      for (int q = 0; q < w.ngates; ++q) apply_gate<Real, WB>(v, w.kind[q], w.l[q], a.mats + 16 * w.mat[q]);
+      for (int m = 0; m < (1 << WB); ++m) v[m] = lds[bw_phys(base + (m << w.b))];
+      apply_gate<Real, WB>(v, w.kind[0], w.l[0], m0);
+      if (w.ngates > 1) apply_gate<Real, WB>(v, w.kind[1], w.l[1], m1);
+      if (w.ngates > 2) apply_gate<Real, WB>(v, w.kind[2], w.l[2], m2);
 #pragma unroll
-      for (int m = 0; m < (1 << WB); ++m) lds[bw_phys(base + (m << b))] = v[m];
+      for (int m = 0; m < (1 << WB); ++m) lds[bw_phys(base + (m << w.b))] = v[m];
     }
     __syncthreads();
   }
   const C rot = mk<Real>(static_cast<Real>(a.rot_re), static_cast<Real>(a.rot_im));
   const C pc = mk<Real>(static_cast<Real>(a.psi_coef_re), static_cast<Real>(a.psi_coef_im));
   const C* __restrict__ psi = static_cast<const C*>(a.psi);
-  for (int j = tid; j < N; j += BW_T) {
+  for (int j = tid; j < N; j += T) {
     const uint32_t g = tm.g(j);
     C x = lds[bw_phys(j)];
     if (a.flags & BW_ROT) x = cmul(x, rot);
@@ -133,30 +165,32 @@ __global__ void __launch_bounds__(BW_T) bw_pass_kernel(BwPassArgs a) {
   }
 }
 
-template <typename Real, int WB>
+template <typename Real, int WB, int TB>
 hipError_t launch_bw_t(const BwPassArgs& a, unsigned ntiles, hipStream_t s) {
   const size_t shmem = size_t((1 << a.n) + (1 << (a.n - 4 > 0 ? a.n - 4 : 0)) + 1) * sizeof(cpx<Real>);
-  auto kern = bw_pass_kernel<Real, WB>;
+  auto kern = bw_pass_kernel<Real, WB, TB>;
   if (shmem > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(kern, dim3(ntiles), dim3(BW_T), shmem, s, a);
+  hipLaunchKernelGGL(kern, dim3(ntiles), dim3(1 << TB), shmem, s, a);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t bw_launch_pass(const BwPassArgs& a, bool c64_dt, int wb, unsigned ntiles, hipStream_t s) {
+  // complex64: 512 threads for large tiles; complex128 keeps 256 (register budget)
   if (c64_dt) {
-    if (wb == 4) return launch_bw_t<float, 4>(a, ntiles, s);
-    if (wb == 3) return launch_bw_t<float, 3>(a, ntiles, s);
-    if (wb == 2) return launch_bw_t<float, 2>(a, ntiles, s);
+    const bool big = a.n >= 12;
+    if (wb == 4) return big ? launch_bw_t<float, 4, 9>(a, ntiles, s) : launch_bw_t<float, 4, 8>(a, ntiles, s);
+    if (wb == 3) return launch_bw_t<float, 3, 8>(a, ntiles, s);
+    if (wb == 2) return launch_bw_t<float, 2, 8>(a, ntiles, s);
   } else {
-    if (wb == 4) return launch_bw_t<double, 4>(a, ntiles, s);
-    if (wb == 3) return launch_bw_t<double, 3>(a, ntiles, s);
-    if (wb == 2) return launch_bw_t<double, 2>(a, ntiles, s);
+    if (wb == 4) return launch_bw_t<double, 4, 8>(a, ntiles, s);
+    if (wb == 3) return launch_bw_t<double, 3, 8>(a, ntiles, s);
+    if (wb == 2) return launch_bw_t<double, 2, 8>(a, ntiles, s);
   }
   return hipErrorInvalidValue;
 }
@@ -201,7 +235,7 @@ void pack_windows(std::vector<std::array<int, 3>> gates, int n, int wb, std::vec
     BwWindow w{};
     w.b = static_cast<int8_t>(b);
     w.ngates = 0;
-    while (i < gates.size() && gates[i][0] + gates[i][1] <= b + wb && w.ngates < 4) {
+    while (i < gates.size() && gates[i][0] + gates[i][1] <= b + wb && w.ngates < 3) {
       w.kind[w.ngates] = static_cast<int8_t>(gates[i][1]);
       w.l[w.ngates] = static_cast<int8_t>(gates[i][0] - b);
       w.mat[w.ngates] = static_cast<int16_t>(gates[i][2]);
@@ -224,7 +258,7 @@ struct BwProgram {
   };
   int npass = 0;
   Pass pass[2];  // [0] applied first (right block), [1] second (left block)
-  c128* mats = nullptr;
+  void* mats = nullptr;  // 16-entry matrices, complex64 or complex128 (rounded once)
   bool c64 = true;
 
   ~BwProgram() {
@@ -259,8 +293,15 @@ fq_status build_program(floquet_op* op, bool c64_dt, std::shared_ptr<BwProgram>*
       (layer == 0 ? refs_b : refs_a).push_back({sites[0], w, mi++});
     }
   }
-  FQ_HIP_CHECK(hipMalloc(&prog->mats, mats.size() * sizeof(c128)));
-  FQ_HIP_CHECK(hipMemcpy(prog->mats, mats.data(), mats.size() * sizeof(c128), hipMemcpyHostToDevice));
+  if (c64_dt) {
+    std::vector<c64> m32(mats.size());
+    for (size_t i = 0; i < mats.size(); ++i) m32[i] = mk<float>(float(mats[i].x), float(mats[i].y));
+    FQ_HIP_CHECK(hipMalloc(&prog->mats, m32.size() * sizeof(c64)));
+    FQ_HIP_CHECK(hipMemcpy(prog->mats, m32.data(), m32.size() * sizeof(c64), hipMemcpyHostToDevice));
+  } else {
+    FQ_HIP_CHECK(hipMalloc(&prog->mats, mats.size() * sizeof(c128)));
+    FQ_HIP_CHECK(hipMemcpy(prog->mats, mats.data(), mats.size() * sizeof(c128), hipMemcpyHostToDevice));
+  }
 
   const int nmax = c64_dt ? 13 : 12;
   auto tile_bit_lo = [&](int site) { return L - site; };  // right/single pass: identity
