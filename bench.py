@@ -6,9 +6,14 @@ bandwidth against the HBM roofline.
 Workload: kicked Ising, L = 20 (d = 1,048,576), J ~ U[0.8, 1.2],
 h ~ U[-1, 1], g = 0.9, periodic, seed 3000, target phi = 0, nev = 100,
 ncv = 220, tol = 1e-10.  The filter order follows the paper's rule
-k = 0.8 * 2^{L+1} / ncv (Sec. 5) = 7625; at the nominal k = 400 with
+k = 0.8 * 2^{L+1} / ncv (Sec. 5) = 7626; at the nominal k = 400 with
 ncv = 220 the apple-line ratio 2d/((k+1) ncv) is 24 and Krylov-Schur
-stagnates, so no time-to-solution exists there.
+stagnates (the worst Ritz estimate stays near 5e-2 over 200 restarts), so
+no time-to-solution exists there.
+
+Other modes: --workload ki_batched (the 1024-problem disorder workload in one
+batched call), --workload bw_L24 (the brickwork filter at L = 24),
+--scan-L L (an (ncv, k) runtime scan), --profile-filter (for counter runs).
 
 One step = one complete arnoldi_eigs solve (filter, CGS2, restart, Ritz
 vectors, FP64 residuals, refinement) in complex64 + FP64 refinement.
@@ -48,8 +53,9 @@ def parse():
     ap.add_argument("--roofline-steps", type=int, default=2000)
     ap.add_argument("--scan-L", type=int, default=None,
                     help="(n_cv, k) scan of the brickwork circuit at this L (n_ev=50, z=1, complex128)")
-    ap.add_argument("--workload", default="ki_L20", choices=["ki_L20", "ki_batched"],
-                    help="ki_batched: 256 realisations x 4 targets, L in 12..16, one batched call")
+    ap.add_argument("--workload", default="ki_L20", choices=["ki_L20", "ki_batched", "bw_L24"],
+                    help="ki_batched: 256 realisations x 4 targets, L in 12..16, one batched call; "
+                         "bw_L24: the brickwork filter (k=300) at L=24")
     ap.add_argument("--profile-filter", action="store_true",
                     help="only the complex64 Horner filter (k=200) and a 64 MiB device copy, for counter runs")
     return ap.parse_args()
@@ -256,6 +262,71 @@ def batched(args):
     print(json.dumps(line))
 
 
+def brickwork_filter(args):
+    """Filter throughput of the brickwork circuit at L = 24 (d = 16,777,216),
+    the size of the circuit workload: k = 300 Horner steps of g_k(U) psi in
+    complex64 (timed steps) and complex128.  One Horner step is two tile
+    passes (right block: read + write w; left block: read w and psi, write w),
+    5 * d * s algorithmic bytes, and 32 * L * d real flops (each of the L
+    two-site gates acts on all d amplitudes as 4x4 complex products).  The
+    full eigen-solve at this size is out of reach at any converging filter
+    order (the paper's rule gives k = 268,435 with ncv = 100)."""
+    import numpy as np
+    import torch
+
+    from paper_2102_05054_amd import brickwork
+    from workloads import CONFIGS
+    from workloads import brickwork as bw_params
+    c = CONFIGS["bw_L24"]
+    L, k = c["L"], c["k"]
+    d = 2 ** L
+    p = bw_params(L, c["seed"])
+    op = brickwork(L, p.gates)
+    s = torch.cuda.Stream()
+    out = {}
+    for name, dt, size in (("c64", torch.complex64, 8), ("c128", torch.complex128, 16)):
+        with torch.cuda.stream(s):
+            x = torch.randn(d, dtype=dt, device="cuda")
+            y = torch.empty_like(x)
+            for _ in range(max(1, args.warmup)):
+                op.apply_filter(x, 4, 0.0, out=y, stream=s)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            steps = args.steps if name == "c64" else 1
+            e0.record(s)
+            for _ in range(steps):
+                op.apply_filter(x, k, 0.0, out=y, stream=s)
+            e1.record(s)
+            s.synchronize()
+        ms = e0.elapsed_time(e1)
+        us_step = 1e3 * ms / (steps * k)
+        out[name] = {"us_per_horner_step": us_step, "U_apps_per_s": 1e6 / us_step,
+                     "alg_GBs": 5 * d * size / (us_step * 1e3),
+                     "TFLOPs": 32 * L * d / (us_step * 1e6), "filter_apps": steps, "ms": ms}
+        del x, y
+    op.close()
+    c64 = out["c64"]
+    line = {
+        "metric": "U-applications/s and HBM GB/s of the brickwork filter at L=24",
+        "value": c64["U_apps_per_s"],
+        "unit": "U-applications/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": max(1, args.warmup),
+        "ms_per_step": c64["ms"] / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic (seeded Haar-random two-site gates)",
+        "config": {"workload": f"brickwork Haar circuit L={L} (d={d}), filter k={k}, phi=0, one step = one "
+                               f"filter application", "L": L, "k": k},
+        "roofline": {"bound": "hbm", "achieved": c64["alg_GBs"], "peak": 8000.0, "unit": "GB/s",
+                     "frac": c64["alg_GBs"] / 8000.0, "traffic": None,
+                     "kernel": "bw_pass_kernel (right block + left block per Horner step)",
+                     "flops_TFLOPs": c64["TFLOPs"], "flops_peak_TFLOPs": 157.3,
+                     "flops_frac": c64["TFLOPs"] / 157.3},
+        "c128": out["c128"],
+    }
+    print(json.dumps(line))
+
+
 def cpu_baseline(p, seconds=15.0):
     """The oracle's matrix-free U (complex128 NumPy) on the host: U-apps/s on a
     bounded sample of the same state size."""
@@ -299,6 +370,9 @@ def main():
         return
     if args.workload == "ki_batched":
         batched(args)
+        return
+    if args.workload == "bw_L24":
+        brickwork_filter(args)
         return
     L = args.L
     k = args.k if args.k is not None else int(math.floor(0.8 * 2 ** (L + 1) / args.ncv))
