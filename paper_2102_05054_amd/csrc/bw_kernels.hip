@@ -165,6 +165,120 @@ __global__ void __launch_bounds__(1 << TB) bw_pass_kernel(BwPassArgs a) {
   }
 }
 
+// Persistent, software-pipelined form for complex64 tiles of 2^NB amplitudes
+// (NB known at compile time): each workgroup walks its tiles (XCD-aware
+// order), and while the windows of one tile run in LDS the next tile is
+// already on its way into registers and psi of the current tile is fetched.
+// Tiles are disjoint, so in-place passes (xin == xout) stay correct.
+template <typename Real, int WB, int TB, int NB, bool PSI>
+__global__ void __launch_bounds__(1 << TB)
+    bw_pipe_kernel(BwPassArgs a, unsigned ntiles, const cpx<Real>* __restrict__ mats, const BwWindow* __restrict__ wins,
+                   cpx<Real>* __restrict__ xout) {
+  using C = cpx<Real>;
+  constexpr int T = 1 << TB, N = 1 << NB, NPT = N / T;
+  static_assert(NPT >= 1 && N % T == 0, "tile must cover the workgroup");
+  extern __shared__ char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int tid = threadIdx.x;
+  // xin may equal xout (in-place pass): read through the same restrict pointer
+  const C* xin = xout == a.xin ? xout : static_cast<const C*>(a.xin);
+  const C* psi = static_cast<const C*>(a.psi);
+  constexpr bool add_psi = PSI;
+  const C rot = mk<Real>(static_cast<Real>(a.rot_re), static_cast<Real>(a.rot_im));
+  const C pc = mk<Real>(static_cast<Real>(a.psi_coef_re), static_cast<Real>(a.psi_coef_im));
+  unsigned bid = blockIdx.x;
+  if (bid >= ntiles) return;
+  TileMap tm = make_tile_map(xcd_tile(bid, ntiles), NB, a.c, a.p);
+  // psi of the current tile is prefetched too when registers allow (<= 16
+  // amplitudes per thread); otherwise it is read in the store loop
+  constexpr bool PSI_PF = PSI && NPT <= 16;
+  C pf[NPT], ps[PSI_PF ? NPT : 1];
+#pragma unroll
+  for (int i = 0; i < NPT; ++i) pf[i] = xin[tm.g(tid + i * T)];
+  constexpr int ngroups = N >> WB;
+  for (;;) {
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) lds[bw_phys(tid + i * T)] = pf[i];
+    if constexpr (PSI_PF) {
+#pragma unroll
+      for (int i = 0; i < NPT; ++i) ps[i] = psi[tm.g(tid + i * T)];
+    }
+    const unsigned nbid = bid + gridDim.x;
+    const bool more = nbid < ntiles;
+    TileMap tn = tm;
+    if (more) {
+      tn = make_tile_map(xcd_tile(nbid, ntiles), NB, a.c, a.p);
+#pragma unroll
+      for (int i = 0; i < NPT; ++i) pf[i] = xin[tn.g(tid + i * T)];
+    }
+    __syncthreads();
+    for (int wi = 0; wi < a.nwin; ++wi) {
+      const WinU w = load_window(wins + wi);
+      C m0[16], m1[16];
+      load_mat<Real>(m0, mats, w.mat[0]);
+      if (w.ngates > 1) load_mat<Real>(m1, mats, w.mat[1]);
+      const uint32_t below = (1u << w.b) - 1u;
+#pragma unroll 1
+      for (int gi = 0; gi < ngroups / T; ++gi) {
+        const int g = tid + gi * T;
+        const int base = static_cast<int>((uint32_t(g) & below) | ((uint32_t(g) >> w.b) << (w.b + WB)));
+        C v[1 << WB];
+#pragma unroll
+        for (int m = 0; m < (1 << WB); ++m) v[m] = lds[bw_phys(base + (m << w.b))];
+        apply_gate<Real, WB>(v, w.kind[0], w.l[0], m0);
+        if (w.ngates > 1) apply_gate<Real, WB>(v, w.kind[1], w.l[1], m1);
+#pragma unroll
+        for (int m = 0; m < (1 << WB); ++m) lds[bw_phys(base + (m << w.b))] = v[m];
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int j = tid + i * T;
+      C x = lds[bw_phys(j)];
+      if (a.flags & BW_ROT) x = cmul(x, rot);
+      if constexpr (PSI) {
+        C p;
+        if constexpr (PSI_PF)
+          p = ps[i];
+        else
+          p = psi[tm.g(j)];
+        x = (a.flags & BW_PSI_COEF) ? cfma(p, pc, x) : cadd(x, p);
+      }
+      xout[tm.g(j)] = x;
+    }
+    if (!more) break;
+    __syncthreads();
+    bid = nbid;
+    tm = tn;
+  }
+}
+
+template <typename Real, int WB, int TB, int NB, bool PSI>
+hipError_t launch_bw_pipe(const BwPassArgs& a, unsigned ntiles, hipStream_t s) {
+  static int wgs_per_pass = 0;  // resident workgroups per pass (CUs x workgroups per CU)
+  const size_t shmem = size_t((1 << NB) + (1 << (NB - 4)) + 1) * sizeof(cpx<Real>);
+  auto kern = bw_pipe_kernel<Real, WB, TB, NB, PSI>;
+  if (wgs_per_pass == 0) {
+    if (shmem > 65536) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem));
+      if (e != hipSuccess) return e;
+    }
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), 1 << TB, shmem);
+    if (e != hipSuccess) return e;
+    wgs_per_pass = std::max(8, (cus * std::max(1, per_cu)) & ~7);
+  }
+  const unsigned grid = std::min<unsigned>(ntiles, static_cast<unsigned>(wgs_per_pass));
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(1 << TB), shmem, s, a, ntiles, static_cast<const cpx<Real>*>(a.mats),
+                     a.wins, static_cast<cpx<Real>*>(a.xout));
+  return hipGetLastError();
+}
+
 template <typename Real, int WB, int TB>
 hipError_t launch_bw_t(const BwPassArgs& a, unsigned ntiles, hipStream_t s) {
   const size_t shmem = size_t((1 << a.n) + (1 << (a.n - 4 > 0 ? a.n - 4 : 0)) + 1) * sizeof(cpx<Real>);
@@ -184,6 +298,13 @@ hipError_t bw_launch_pass(const BwPassArgs& a, bool c64_dt, int wb, unsigned nti
   // complex64: 512 threads for large tiles; complex128 keeps 256 (register budget)
   if (c64_dt) {
     const bool big = a.n >= 12;
+    // pipelined persistent form when every workgroup gets several tiles
+    if (wb == 4 && ntiles >= 1024 && ntiles % 8 == 0 && (a.n == 13 || a.n == 14)) {
+      const bool ps = (a.flags & BW_ADD_PSI) != 0;
+      if (a.n == 13)
+        return ps ? launch_bw_pipe<float, 4, 9, 13, true>(a, ntiles, s) : launch_bw_pipe<float, 4, 9, 13, false>(a, ntiles, s);
+      return ps ? launch_bw_pipe<float, 4, 9, 14, true>(a, ntiles, s) : launch_bw_pipe<float, 4, 9, 14, false>(a, ntiles, s);
+    }
     if (wb == 4) return big ? launch_bw_t<float, 4, 9>(a, ntiles, s) : launch_bw_t<float, 4, 8>(a, ntiles, s);
     if (wb == 3) return launch_bw_t<float, 3, 8>(a, ntiles, s);
     if (wb == 2) return launch_bw_t<float, 2, 8>(a, ntiles, s);
@@ -235,7 +356,7 @@ void pack_windows(std::vector<std::array<int, 3>> gates, int n, int wb, std::vec
     BwWindow w{};
     w.b = static_cast<int8_t>(b);
     w.ngates = 0;
-    while (i < gates.size() && gates[i][0] + gates[i][1] <= b + wb && w.ngates < 3) {
+    while (i < gates.size() && gates[i][0] + gates[i][1] <= b + wb && w.ngates < 2) {
       w.kind[w.ngates] = static_cast<int8_t>(gates[i][1]);
       w.l[w.ngates] = static_cast<int8_t>(gates[i][0] - b);
       w.mat[w.ngates] = static_cast<int16_t>(gates[i][2]);
