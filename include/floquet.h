@@ -125,6 +125,11 @@ typedef struct {
   unsigned long long seed; /* start vector seed when v0_dev is NULL */
   const void* v0_dev;      /* optional complex128 start vector (d), or NULL */
   int refine_k;            /* filter order of the FP64 refinement (0: k) */
+  const double* poly_coeffs; /* optional host array of k+1 complex128 a_0..a_k (interleaved re,
+                                im): the Arnoldi filter becomes sum_m a_m U^m (Sec. 3, Eq. (poly),
+                                e.g. a damped kernel) instead of the geometric sum; the pairs of
+                                largest |p(omega)| are returned, ordered by arc distance to phi.
+                                NULL: geometric sum.  Needs refine_k = 0 or k. */
 } fq_arnoldi_opts;
 
 /* Counters and per-phase wall times (seconds) of one solve. */

@@ -35,7 +35,7 @@ class FqArnoldiOpts(ctypes.Structure):
     _fields_ = [
         ("k", c_int), ("ncv", c_int), ("tol", c_double), ("max_restarts", c_int),
         ("filter_dtype", c_int), ("refine", c_int), ("seed", c_ulonglong), ("v0_dev", c_void_p),
-        ("refine_k", c_int),
+        ("refine_k", c_int), ("poly_coeffs", POINTER(c_double)),
     ]
 
 

@@ -122,13 +122,22 @@ class FloquetOp:
     def arnoldi_eigs(self, nev: int, phi: float, *, k: int, ncv: int, tol: float = 1e-10,
                      max_restarts: int = 200, filter_dtype: str = "c128", refine: bool = True,
                      seed: int = 0, v0=None, want_vectors: bool = True, stream=None,
-                     allow_not_converged: bool = False, refine_k: int = 0):
-        """Eigenpairs of U closest to e^{i phi}.  Returns (evals, evecs, resid, stats, status)."""
+                     allow_not_converged: bool = False, refine_k: int = 0, poly=None):
+        """Eigenpairs of U closest to e^{i phi}.  Returns (evals, evecs, resid, stats, status).
+
+        ``poly`` (optional): coefficients a_0..a_k of the filter sum_m a_m U^m used
+        instead of the geometric sum (k is then len(poly) - 1)."""
         torch = _torch()
+        pc = None
+        if poly is not None:
+            c = np.asarray(poly, dtype=np.complex128)
+            k = len(c) - 1
+            pc, pcp = _dbl_array(np.stack([c.real, c.imag], axis=1).reshape(-1))
         opts = FqArnoldiOpts(k=int(k), ncv=int(ncv), tol=float(tol), max_restarts=int(max_restarts),
                              filter_dtype=FQ_C64 if filter_dtype == "c64" else FQ_C128,
                              refine=1 if refine else 0, seed=int(seed),
-                             v0_dev=c_void_p(v0.data_ptr()) if v0 is not None else None, refine_k=int(refine_k))
+                             v0_dev=c_void_p(v0.data_ptr()) if v0 is not None else None, refine_k=int(refine_k),
+                             poly_coeffs=pcp if pc is not None else None)
         if v0 is not None:
             self._check_state(v0, "v0")
             if v0.dtype != torch.complex128:
@@ -185,7 +194,7 @@ def brickwork(L: int, gates) -> FloquetOp:
 def arnoldi_eigs_batched(ops: Sequence[FloquetOp], phis: Sequence[float], nev: int, *, k, ncv: int,
                          tol: float = 1e-10, max_restarts: int = 200, filter_dtype: str = "c128",
                          refine: bool = True, seed: int = 0, want_vectors: bool = False, stream=None,
-                         allow_not_converged=False, refine_k: int = 0):
+                         allow_not_converged=False, refine_k: int = 0, poly=None):
     """All (op, phi) problems in one call.
 
     ``k`` is one filter order for every op or a sequence with one per op.
@@ -197,6 +206,11 @@ def arnoldi_eigs_batched(ops: Sequence[FloquetOp], phis: Sequence[float], nev: i
     n_ops, n_phi = len(ops), len(phis)
     handles = (c_void_p * n_ops)(*[o.handle for o in ops])
     ph, php = _dbl_array(phis)
+    pc = None
+    if poly is not None:
+        c = np.asarray(poly, dtype=np.complex128)
+        k = len(c) - 1
+        pc, pcp = _dbl_array(np.stack([c.real, c.imag], axis=1).reshape(-1))
     if np.ndim(k) == 0:
         kk = None
         k0 = int(k)
@@ -207,7 +221,8 @@ def arnoldi_eigs_batched(ops: Sequence[FloquetOp], phis: Sequence[float], nev: i
         k0 = int(k[0])
     opts = FqArnoldiOpts(k=k0, ncv=int(ncv), tol=float(tol), max_restarts=int(max_restarts),
                          filter_dtype=FQ_C64 if filter_dtype == "c64" else FQ_C128,
-                         refine=1 if refine else 0, seed=int(seed), v0_dev=None, refine_k=int(refine_k))
+                         refine=1 if refine else 0, seed=int(seed), v0_dev=None, refine_k=int(refine_k),
+                         poly_coeffs=pcp if pc is not None else None)
     evals = np.zeros(n_ops * n_phi * 2 * nev)
     resid = np.zeros(n_ops * n_phi * nev)
     stats = (FqArnoldiStats * (n_ops * n_phi))()

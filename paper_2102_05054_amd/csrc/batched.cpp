@@ -785,6 +785,10 @@ fq_status arnoldi_batched_solve(floquet_op* const* ops, int n_ops, const double*
     set_error("arnoldi_eigs_batched: opts.v0_dev must be NULL (each problem uses the seeded start vector)");
     return FQ_EINVAL;
   }
+  if (o->poly_coeffs && k_per_op) {
+    set_error("arnoldi_eigs_batched: a user polynomial fixes the filter order: k_per_op must be NULL");
+    return FQ_EINVAL;
+  }
   std::vector<int> ks(n_ops);
   for (int i = 0; i < n_ops; ++i) {
     fq_arnoldi_opts oi = *o;
@@ -827,7 +831,9 @@ fq_status arnoldi_batched_solve(floquet_op* const* ops, int n_ops, const double*
     for (int i = 0; i < n_ops; ++i) {
       floquet_op* op = ops[i];
       // the batched basis products run on the matrix cores only (<= 256 columns)
-      if (op->model != FQ_KICKED_ISING || op->L < 4 || nev > 256 || keep_count(o->ncv, nev) > 256) {
+      // (user polynomials run one by one as well)
+      if (op->model != FQ_KICKED_ISING || op->L < 4 || nev > 256 || keep_count(o->ncv, nev) > 256 ||
+          o->poly_coeffs) {
         if (j0 == 0)
           for (int j = 0; j < n_phi; ++j) seq.emplace_back(i, j);
         continue;

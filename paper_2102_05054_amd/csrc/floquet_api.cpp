@@ -460,13 +460,13 @@ fq_status ensure_scratch32(floquet_op* op) {
   return FQ_OK;
 }
 
-fq_status filter_mixed(floquet_op* op, int k, double phi, fq_dtype dt, const void* psi64, void* out64,
-                       hipStream_t s) {
-  if (dt == FQ_C128) return filter_internal(op, k, phi, nullptr, FQ_C128, psi64, out64, s);
+fq_status filter_mixed(floquet_op* op, int k, double phi, const zd* coefs, fq_dtype dt, const void* psi64,
+                       void* out64, hipStream_t s) {
+  if (dt == FQ_C128) return filter_internal(op, k, phi, coefs, FQ_C128, psi64, out64, s);
   fq_status st = ensure_scratch32(op);
   if (st != FQ_OK) return st;
   FQ_HIP_CHECK(launch_cast_c128_to_c64(psi64, op->psi32, op->dim(), s));
-  st = filter_internal(op, k, phi, nullptr, FQ_C64, op->psi32, op->out32, s);
+  st = filter_internal(op, k, phi, coefs, FQ_C64, op->psi32, op->out32, s);
   if (st != FQ_OK) return st;
   FQ_HIP_CHECK(launch_cast_c64_to_c128(op->out32, out64, op->dim(), s));
   return FQ_OK;

@@ -214,9 +214,10 @@ fq_status normalize_col(const Ws& ws, int j, double* nrm_host, hipStream_t s) {
 }
 
 // One Arnoldi extension step j: V[:, j+1] and the coefficients of column j.
-fq_status arnoldi_step(floquet_op* op, const Ws& ws, int j, int k, double phi, fq_dtype dt, hipStream_t s) {
+fq_status arnoldi_step(floquet_op* op, const Ws& ws, int j, int k, double phi, const zd* coefs, fq_dtype dt,
+                       hipStream_t s) {
   const c128* vj = ws.V + size_t(j) * ws.d;
-  FQ_TRY(filter_mixed(op, k, phi, dt, vj, ws.w, s));
+  FQ_TRY(filter_mixed(op, k, phi, coefs, dt, vj, ws.w, s));
   const int nc = j + 1;
   FQ_HIP_CHECK(launch_dots(ws.V, ws.d, nc, ws.w, ws.d, ws.partial, ws.ldp, s));
   FQ_HIP_CHECK(launch_reduce_cols(ws.partial, ws.ldp, ws.nblk, nc, slot_h1(ws, j), s));
@@ -286,6 +287,7 @@ struct Solver {
   Ws ws;
   int nev, ncv, k, max_restarts;
   double phi;
+  std::vector<zd> coefs;  // user polynomial a_0..a_k, or empty for the geometric sum
   hipStream_t s;
   fq_arnoldi_stats* st;
   double t_filter = 0, t_orth = 0, t_restart = 0;
@@ -309,7 +311,7 @@ struct Solver {
       const double t0 = now_s();
       int copied = kk;  // columns of H already on the host
       for (int j = kk; j < m; ++j) {
-        FQ_TRY(arnoldi_step(op, ws, j, k, phi, dt, s));
+        FQ_TRY(arnoldi_step(op, ws, j, k, phi, coefs.empty() ? nullptr : coefs.data(), dt, s));
         st->n_filter_apps += 1;
         st->n_U_apps += k;
         if (dt == FQ_C64) st->n_U_apps_c64 += k;
@@ -444,6 +446,17 @@ fq_status validate_arnoldi(const floquet_op* op, int nev, const fq_arnoldi_opts*
               "max_restarts >= 0");
     return FQ_EINVAL;
   }
+  if (o->poly_coeffs) {
+    if (o->refine_k != 0 && o->refine_k != o->k) {
+      set_error("arnoldi_eigs: a user polynomial needs refine_k = 0 (the refinement uses the same polynomial)");
+      return FQ_EINVAL;
+    }
+    for (int i = 0; i < 2 * (o->k + 1); ++i)
+      if (!std::isfinite(o->poly_coeffs[i])) {
+        set_error("arnoldi_eigs: polynomial coefficients must be finite");
+        return FQ_EINVAL;
+      }
+  }
   return FQ_OK;
 }
 
@@ -481,6 +494,8 @@ fq_status arnoldi_solve(floquet_op* op, int nev, double phi, const fq_arnoldi_op
   sv.s = s;
   sv.st = st;
   sv.seed = o->seed;
+  if (o->poly_coeffs)
+    for (int i = 0; i <= o->k; ++i) sv.coefs.push_back(zd(o->poly_coeffs[2 * i], o->poly_coeffs[2 * i + 1]));
   FQ_TRY(ensure_ws(op, o->ncv, nev, evecs_dev, &sv.ws, &temp));
   const size_t d = op->dim();
 

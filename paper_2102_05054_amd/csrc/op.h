@@ -99,9 +99,10 @@ fq_status apply_U_internal(floquet_op* op, fq_dtype dt, const void* psi, void* o
 // otherwise the polynomial with k+1 host coefficients (phi ignored).
 fq_status filter_internal(floquet_op* op, int k, double phi, const zd* coefs, fq_dtype dt,
                           const void* psi, void* out, hipStream_t s);
-// FP64 state in, FP64 state out, filter arithmetic in dt (casts around it for c64).
-fq_status filter_mixed(floquet_op* op, int k, double phi, fq_dtype dt, const void* psi64, void* out64,
-                       hipStream_t s);
+// FP64 state in, FP64 state out, filter arithmetic in dt (casts around it for c64);
+// coefs as for filter_internal.
+fq_status filter_mixed(floquet_op* op, int k, double phi, const zd* coefs, fq_dtype dt, const void* psi64,
+                       void* out64, hipStream_t s);
 fq_status ensure_scratch32(floquet_op* op);
 // out = a * psi
 fq_status poly_scale_copy(floquet_op* op, zd a, fq_dtype dt, const void* psi, void* out, hipStream_t s);

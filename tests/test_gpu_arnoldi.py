@@ -73,3 +73,47 @@ def test_refinement_filter_order():
     assert st["n_U_apps_c64"] % 40 == 0
     # FP64 part: refinement filter applications of order 20 plus nev = 8 U per Ritz check
     assert st["n_U_apps"] > st["n_U_apps_c64"]
+
+
+@pytest.mark.parametrize("filter_dtype", ["c128", "c64"])
+def test_user_polynomial_filter(filter_dtype):
+    # A Fejer-damped one-sided sum centred at phi as the Arnoldi filter
+    # (Eq. (poly)): the pairs of largest |p(omega)|, from zgeev's spectrum.
+    L, nev, k, phi = 10, 8, 60, 1.1
+    p = kicked_ising(L, 88)
+    U = models.ki_dense(p)
+    w = np.linalg.eigvals(U)
+    m = np.arange(k + 1)
+    a = (1 - m / (k + 1)) * np.exp(-1j * m * phi)
+    pv = np.abs(np.polyval(a[::-1], w))
+    order = np.argsort(-pv)
+    assert (pv[order[nev - 1]] - pv[order[nev]]) > 1e-3 * pv[order[0]]  # a clear selection gap
+    want = w[order[:nev]]
+    with ki_op(p) as op:
+        ev, _, res, st, status = op.arnoldi_eigs(nev, phi, k=0, ncv=30, tol=1e-10, filter_dtype=filter_dtype,
+                                                 seed=2, want_vectors=False, poly=a)
+    _match(ev, want, 1e-12)
+    assert res.max() <= 1e-10
+    # the output is ordered by arc distance to phi
+    arc = np.abs(np.angle(ev * np.exp(-1j * phi)))
+    assert np.all(np.diff(arc) >= 0)
+
+
+def test_user_polynomial_filter_batched():
+    from paper_2102_05054_amd import arnoldi_eigs_batched
+    L, nev, k = 9, 5, 40
+    params = [kicked_ising(L, 91), kicked_ising(L, 92)]
+    phi = 2.5
+    m = np.arange(k + 1)
+    a = (1 - m / (k + 1)) * np.exp(-1j * m * phi)
+    ops = [ki_op(q) for q in params]
+    try:
+        ev, res, stats, st = arnoldi_eigs_batched(ops, [phi], nev, k=k, ncv=20, tol=1e-10, filter_dtype="c64", poly=a)
+        for i, q in enumerate(params):
+            w = np.linalg.eigvals(models.ki_dense(q))
+            pv = np.abs(np.polyval(a[::-1], w))
+            _match(ev[i, 0], w[np.argsort(-pv)[:nev]], 1e-12)
+            assert res[i, 0].max() <= 1e-10
+    finally:
+        for o in ops:
+            o.close()

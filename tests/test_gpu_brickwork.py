@@ -8,7 +8,8 @@ import pytest
 
 from gpu_util import bw_op, rel, require_gpu, say, to_dev, to_np
 from oracle import eig, filters, models
-from workloads import brickwork, brickwork_from_matrices, brickwork_layout, haar_unitary, random_state
+from workloads import (brickwork, brickwork_cz, brickwork_from_matrices, brickwork_layout, haar_unitary,
+                       random_state)
 
 pytestmark = pytest.mark.gpu
 
@@ -133,3 +134,32 @@ def test_arnoldi_brickwork_L10(filter_dtype):
     assert res.max() <= 1e-10
     for n in range(nev):
         assert np.linalg.norm(U @ vecs[n] - ev[n] * vecs[n]) < 1e-10
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("L", [7, 10, 16])
+def test_other_gate_set_parity(dt, L):
+    # controlled-Z entanglers dressed with random one-site rotations: U and the
+    # Horner filter against the oracle (dense for L <= 12, matrix-free above)
+    say(f"bw CZ gate set L={L} {dt}")
+    p = brickwork_cz(L, 300 + L)
+    psi = random_state(2 ** L, 12)[0]
+    mv = (lambda v, U=models.bw_dense(p): U @ v) if L <= 12 else (lambda v: models.bw_apply(p, v))
+    with bw_op(p) as op:
+        out_u = to_np(op.apply_U(to_dev(psi, _dt(dt))))
+        out_f = to_np(op.apply_filter(to_dev(psi, _dt(dt)), 12, 0.7))
+    assert rel(out_u, mv(psi)) < TOL_U[dt]
+    tol = 1e-12 * 13 if dt == "c128" else 2e-7 * 13 + 3e-6
+    assert rel(out_f, filters.geometric_sum(mv, psi, 12, 0.7)) < tol
+
+
+def test_other_gate_set_eigenpairs():
+    L, nev = 10, 12
+    p = brickwork_cz(L, 777)
+    U = models.bw_dense(p)
+    om_ref, _ = eig.full_closest(U, nev, 1.9)
+    with bw_op(p) as op:
+        ev, _, res, stats, st = op.arnoldi_eigs(nev, 1.9, k=40, ncv=40, tol=1e-10, seed=3, filter_dtype="c64",
+                                                want_vectors=False)
+    assert np.max(np.abs(ev - om_ref)) < 1e-12
+    assert res.max() <= 1e-10

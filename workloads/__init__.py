@@ -36,6 +36,7 @@ __all__ = [
     "kicked_ising",
     "brickwork",
     "brickwork_layout",
+    "brickwork_cz",
     "haar_unitary",
     "start_vector",
     "random_state",
@@ -116,6 +117,23 @@ def brickwork(L: int, seed: int, *, phi: float = 0.0) -> BrickworkParams:
         u = haar_unitary(2 ** len(sites), rng)
         mats.append(u.reshape(-1))
     return BrickworkParams(L=L, gates=np.concatenate(mats).astype(np.complex128), phi=float(phi))
+
+
+def brickwork_cz(L: int, seed: int, *, phi: float = 0.0) -> BrickworkParams:
+    """Another gate set on the same layout: every two-site gate is a
+    controlled-Z entangler dressed with Haar-random one-site rotations,
+    CZ (r_i x r_{i+1}); the one-site gates are Haar-random."""
+    rng = np.random.default_rng(seed)
+    layer_b, layer_a = brickwork_layout(L)
+    cz = np.diag([1.0, 1.0, 1.0, -1.0]).astype(np.complex128)
+    mats = []
+    for sites in layer_b + layer_a:
+        if len(sites) == 1:
+            mats.append(haar_unitary(2, rng))
+        else:
+            r1, r2 = haar_unitary(2, rng), haar_unitary(2, rng)
+            mats.append(cz @ np.kron(r1, r2))
+    return brickwork_from_matrices(L, mats, phi)
 
 
 def brickwork_from_matrices(L: int, mats: Sequence[np.ndarray], phi: float = 0.0) -> BrickworkParams:
