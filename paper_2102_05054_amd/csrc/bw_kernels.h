@@ -11,24 +11,30 @@ enum : int {
   BW_PSI_COEF = 4,
 };
 
-// One window: up to three gates of one layer inside tile bits [b, b + wb).
-// kind 2 = two-site gate on local bits (l, l+1), local index 2*b_{l+1} + b_l;
-// kind 1 = one-site gate on local bit l.  mat indexes 16-entry matrices.
-struct BwWindow {
-  int8_t b, ngates;
-  int8_t kind[3];
-  int8_t l[3];
-  int16_t mat[3];
-  int16_t pad;
+// One gate of a window: kind 2 = two-site gate on window bits (l, l+1),
+// local index 2*b_{l+1} + b_l; kind 1 = one-site gate on window bit l.  mat
+// indexes the 16-entry matrices.
+struct BwGate {
+  int8_t kind, l;
+  int16_t mat;
 };
-static_assert(sizeof(BwWindow) == 16, "BwWindow is read as one 16-byte word");
+static_assert(sizeof(BwGate) == 4, "BwGate is read as one 32-bit word");
+
+// One window: the gates gates[first .. first + count) act inside tile bits
+// [b, b + WB) and are applied in this order, with the window's 2^WB
+// amplitudes held in registers (one LDS round trip per window).
+struct BwWin {
+  int16_t b, first, count, pad;
+};
+static_assert(sizeof(BwWin) == 8, "BwWin is read as one 64-bit word");
 
 struct BwPassArgs {
   const void* xin;
   void* xout;
   const void* psi;
   const void* mats;  // 16-entry matrices in the pass precision
-  const BwWindow* wins;
+  const BwWin* wins;
+  const BwGate* gates;
   int nwin;
   int n, c, p;
   int flags;

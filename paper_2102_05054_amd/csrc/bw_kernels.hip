@@ -10,10 +10,13 @@
 //   left pass:  tile = a chunk of low bits + global bits [L - c_s, L),
 //               then e^{-i phi} and +psi for the Horner step.
 // One Horner step = right pass (read w, write w) + left pass (read w, read
-// psi, write w).  Inside a tile the gates are applied layer by layer in
-// windows of up to four consecutive tile bits: each thread takes the 16
-// amplitudes of one window group from LDS into registers, applies every gate
-// of the layer that lies in the window, and writes them back.
+// psi, write w).  Inside a tile the gates are applied in windows of WB
+// consecutive tile bits: each thread takes the 2^WB amplitudes of one window
+// group from LDS into registers, applies the window's gates in order, and
+// writes them back.  A host scheduler fills each window with up to two gates
+// of either layer whose bits lie inside it and whose earlier gates on the
+// same sites are done, so any order of local gates (more layers, other gate
+// sets) maps onto the same windows.
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -29,7 +32,7 @@ namespace {
 
 __device__ __forceinline__ int bw_phys(int j) { return j + (j >> 4); }
 
-// 4x4 gate on local bits (L0, L0+1) of a window of WB bits
+// 4x4 gate on window bits (L0, L0+1)
 template <typename Real, int WB, int L0>
 __device__ __forceinline__ void gate2(cpx<Real> (&v)[1 << WB], const cpx<Real> (&m)[16]) {
   constexpr int lo = 1 << L0, hi = 1 << (L0 + 1);
@@ -62,15 +65,17 @@ __device__ __forceinline__ void gate1(cpx<Real> (&v)[1 << WB], const cpx<Real> (
   }
 }
 
+// kind 2: two-site gate on window bits (l, l+1); kind 1: one-site gate on l
 template <typename Real, int WB>
 __device__ __forceinline__ void apply_gate(cpx<Real> (&v)[1 << WB], int kind, int l, const cpx<Real> (&m)[16]) {
-  // kind 2: two-site gate on local bits (l, l+1); kind 1: one-site gate on l
   if (kind == 2) {
     if (l == 0) gate2<Real, WB, 0>(v, m);
     if constexpr (WB >= 3)
       if (l == 1) gate2<Real, WB, 1>(v, m);
     if constexpr (WB >= 4)
       if (l == 2) gate2<Real, WB, 2>(v, m);
+    if constexpr (WB >= 5)
+      if (l == 3) gate2<Real, WB, 3>(v, m);
   } else {
     if (l == 0) gate1<Real, WB, 0>(v, m);
     if (l == 1) gate1<Real, WB, 1>(v, m);
@@ -78,45 +83,70 @@ __device__ __forceinline__ void apply_gate(cpx<Real> (&v)[1 << WB], int kind, in
       if (l == 2) gate1<Real, WB, 2>(v, m);
     if constexpr (WB >= 4)
       if (l == 3) gate1<Real, WB, 3>(v, m);
+    if constexpr (WB >= 5)
+      if (l == 4) gate1<Real, WB, 4>(v, m);
   }
 }
 
-// A window's fields, made wave-uniform (scalar registers) so that the gate
-// dispatch branches on scalars and the matrices can be read with scalar loads.
+// Window and gate fields are made wave-uniform (scalar registers), so that
+// the gate dispatch branches on scalars and the matrices are scalar loads.
 struct WinU {
-  int b, ngates;
-  int kind[3], l[3], mat[3];
+  int b, first, count;
 };
-
-__device__ __forceinline__ WinU load_window(const BwWindow* p) {
-  const int4 raw = *reinterpret_cast<const int4*>(p);
+__device__ __forceinline__ WinU load_win(const BwWin* p) {
+  const int2 raw = *reinterpret_cast<const int2*>(p);
   const int x = __builtin_amdgcn_readfirstlane(raw.x);
   const int y = __builtin_amdgcn_readfirstlane(raw.y);
-  const int z = __builtin_amdgcn_readfirstlane(raw.z);
-  const int t = __builtin_amdgcn_readfirstlane(raw.w);
   WinU w;
-  w.b = x & 0xff;
-  w.ngates = (x >> 8) & 0xff;
-  w.kind[0] = (x >> 16) & 0xff;
-  w.kind[1] = (x >> 24) & 0xff;
-  w.kind[2] = y & 0xff;
-  w.l[0] = (y >> 8) & 0xff;
-  w.l[1] = (y >> 16) & 0xff;
-  w.l[2] = (y >> 24) & 0xff;
-  w.mat[0] = z & 0xffff;
-  w.mat[1] = (z >> 16) & 0xffff;
-  w.mat[2] = t & 0xffff;
+  w.b = static_cast<int16_t>(x & 0xffff);
+  w.first = static_cast<int16_t>((x >> 16) & 0xffff);
+  w.count = static_cast<int16_t>(y & 0xffff);
   return w;
 }
+struct GateU {
+  int kind, l, mat;
+};
+__device__ __forceinline__ GateU load_gate(const BwGate* p) {
+  const int x = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int*>(p));
+  GateU g;
+  g.kind = x & 0xff;
+  g.l = (x >> 8) & 0xff;
+  g.mat = (x >> 16) & 0xffff;
+  return g;
+}
+
+// The (at most two) gates of a window with their matrices, read once per
+// window before the group loop (scalar loads).
+template <typename Real>
+struct WinGates {
+  GateU g0, g1;
+  cpx<Real> m0[16], m1[16];
+};
 
 template <typename Real>
-__device__ __forceinline__ void load_mat(cpx<Real> (&m)[16], const cpx<Real>* __restrict__ mats, int idx) {
+__device__ __forceinline__ void load_win_gates(WinGates<Real>& wg, const WinU& w, const BwGate* __restrict__ gates,
+                                               const cpx<Real>* __restrict__ mats) {
+  wg.g0 = load_gate(gates + w.first);
 #pragma unroll
-  for (int i = 0; i < 16; ++i) m[i] = mats[16 * idx + i];
+  for (int i = 0; i < 16; ++i) wg.m0[i] = mats[16 * wg.g0.mat + i];
+  if (w.count > 1) {
+    wg.g1 = load_gate(gates + w.first + 1);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) wg.m1[i] = mats[16 * wg.g1.mat + i];
+  }
+}
+
+// Apply the window's gates to the group of 2^WB amplitudes held in v.
+template <typename Real, int WB>
+__device__ __forceinline__ void window_gates(cpx<Real> (&v)[1 << WB], const WinU& w, const WinGates<Real>& wg) {
+  apply_gate<Real, WB>(v, wg.g0.kind, wg.g0.l, wg.m0);
+  if (w.count > 1) apply_gate<Real, WB>(v, wg.g1.kind, wg.g1.l, wg.m1);
 }
 
 template <typename Real, int WB, int TB>
-__global__ void __launch_bounds__(1 << TB) bw_pass_kernel(BwPassArgs a) {
+__global__ void __launch_bounds__(1 << TB)
+    bw_pass_kernel(BwPassArgs a, const cpx<Real>* __restrict__ mats, const BwWin* __restrict__ wins,
+                   const BwGate* __restrict__ gates) {
   using C = cpx<Real>;
   constexpr int T = 1 << TB;
   extern __shared__ char smem_raw[];
@@ -127,17 +157,13 @@ __global__ void __launch_bounds__(1 << TB) bw_pass_kernel(BwPassArgs a) {
   const TileMap tm = make_tile_map(tile, a.n, a.c, a.p);
   const C* __restrict__ xin = static_cast<const C*>(a.xin);
   C* __restrict__ xout = static_cast<C*>(a.xout);
-  const C* __restrict__ mats = static_cast<const C*>(a.mats);
   for (int j = tid; j < N; j += T) lds[bw_phys(j)] = xin[tm.g(j)];
   __syncthreads();
   const int ngroups = N >> WB;
   for (int wi = 0; wi < a.nwin; ++wi) {
-    const WinU w = load_window(a.wins + wi);
-    // the window's matrices, read once per window (uniform addresses)
-    C m0[16], m1[16], m2[16];
-    load_mat<Real>(m0, mats, w.mat[0]);
-    if (w.ngates > 1) load_mat<Real>(m1, mats, w.mat[1]);
-    if (w.ngates > 2) load_mat<Real>(m2, mats, w.mat[2]);
+    const WinU w = load_win(wins + wi);
+    WinGates<Real> wg;
+    load_win_gates<Real>(wg, w, gates, mats);
     const uint32_t below = (1u << w.b) - 1u;
     for (int g = tid; g < ngroups; g += T) {
       // insert WB zero bits at position b
@@ -145,9 +171,7 @@ __global__ void __launch_bounds__(1 << TB) bw_pass_kernel(BwPassArgs a) {
       C v[1 << WB];
 #pragma unroll
       for (int m = 0; m < (1 << WB); ++m) v[m] = lds[bw_phys(base + (m << w.b))];
-      apply_gate<Real, WB>(v, w.kind[0], w.l[0], m0);
-      if (w.ngates > 1) apply_gate<Real, WB>(v, w.kind[1], w.l[1], m1);
-      if (w.ngates > 2) apply_gate<Real, WB>(v, w.kind[2], w.l[2], m2);
+      window_gates<Real, WB>(v, w, wg);
 #pragma unroll
       for (int m = 0; m < (1 << WB); ++m) lds[bw_phys(base + (m << w.b))] = v[m];
     }
@@ -165,44 +189,36 @@ __global__ void __launch_bounds__(1 << TB) bw_pass_kernel(BwPassArgs a) {
   }
 }
 
-// Persistent, software-pipelined form for complex64 tiles of 2^NB amplitudes
-// (NB known at compile time): each workgroup walks its tiles (XCD-aware
-// order), and while the windows of one tile run in LDS the next tile is
-// already on its way into registers and psi of the current tile is fetched.
-// Tiles are disjoint, so in-place passes (xin == xout) stay correct.
+// Persistent, software-pipelined form for tiles of 2^NB amplitudes
+// (2^(NB - WB - TB) window groups per thread): each workgroup walks its tiles
+// (XCD-aware order), and while the windows of one tile run in LDS the next
+// tile is already on its way into registers.  Tiles are disjoint, so
+// in-place passes (xin == xout) stay correct.
 template <typename Real, int WB, int TB, int NB, bool PSI>
 __global__ void __launch_bounds__(1 << TB)
-    bw_pipe_kernel(BwPassArgs a, unsigned ntiles, const cpx<Real>* __restrict__ mats, const BwWindow* __restrict__ wins,
-                   cpx<Real>* __restrict__ xout) {
+    bw_pipe_kernel(BwPassArgs a, unsigned ntiles, const cpx<Real>* __restrict__ mats, const BwWin* __restrict__ wins,
+                   const BwGate* __restrict__ gates, cpx<Real>* __restrict__ xout) {
   using C = cpx<Real>;
   constexpr int T = 1 << TB, N = 1 << NB, NPT = N / T;
-  static_assert(NPT >= 1 && N % T == 0, "tile must cover the workgroup");
+  constexpr int GPT = 1 << (NB - WB - TB);  // window groups per thread
+  static_assert(NB - WB >= TB, "every thread owns a window group");
   extern __shared__ char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
   const int tid = threadIdx.x;
   // xin may equal xout (in-place pass): read through the same restrict pointer
   const C* xin = xout == a.xin ? xout : static_cast<const C*>(a.xin);
   const C* psi = static_cast<const C*>(a.psi);
-  constexpr bool add_psi = PSI;
   const C rot = mk<Real>(static_cast<Real>(a.rot_re), static_cast<Real>(a.rot_im));
   const C pc = mk<Real>(static_cast<Real>(a.psi_coef_re), static_cast<Real>(a.psi_coef_im));
   unsigned bid = blockIdx.x;
   if (bid >= ntiles) return;
   TileMap tm = make_tile_map(xcd_tile(bid, ntiles), NB, a.c, a.p);
-  // psi of the current tile is prefetched too when registers allow (<= 16
-  // amplitudes per thread); otherwise it is read in the store loop
-  constexpr bool PSI_PF = PSI && NPT <= 16;
-  C pf[NPT], ps[PSI_PF ? NPT : 1];
+  C pf[NPT];
 #pragma unroll
   for (int i = 0; i < NPT; ++i) pf[i] = xin[tm.g(tid + i * T)];
-  constexpr int ngroups = N >> WB;
   for (;;) {
 #pragma unroll
     for (int i = 0; i < NPT; ++i) lds[bw_phys(tid + i * T)] = pf[i];
-    if constexpr (PSI_PF) {
-#pragma unroll
-      for (int i = 0; i < NPT; ++i) ps[i] = psi[tm.g(tid + i * T)];
-    }
     const unsigned nbid = bid + gridDim.x;
     const bool more = nbid < ntiles;
     TileMap tn = tm;
@@ -213,20 +229,18 @@ __global__ void __launch_bounds__(1 << TB)
     }
     __syncthreads();
     for (int wi = 0; wi < a.nwin; ++wi) {
-      const WinU w = load_window(wins + wi);
-      C m0[16], m1[16];
-      load_mat<Real>(m0, mats, w.mat[0]);
-      if (w.ngates > 1) load_mat<Real>(m1, mats, w.mat[1]);
+      const WinU w = load_win(wins + wi);
+      WinGates<Real> wg;
+      load_win_gates<Real>(wg, w, gates, mats);
       const uint32_t below = (1u << w.b) - 1u;
 #pragma unroll 1
-      for (int gi = 0; gi < ngroups / T; ++gi) {
-        const int g = tid + gi * T;
-        const int base = static_cast<int>((uint32_t(g) & below) | ((uint32_t(g) >> w.b) << (w.b + WB)));
+      for (int gi = 0; gi < GPT; ++gi) {
+        const uint32_t g = uint32_t(tid + gi * T);
+        const int base = static_cast<int>((g & below) | ((g >> w.b) << (w.b + WB)));
         C v[1 << WB];
 #pragma unroll
         for (int m = 0; m < (1 << WB); ++m) v[m] = lds[bw_phys(base + (m << w.b))];
-        apply_gate<Real, WB>(v, w.kind[0], w.l[0], m0);
-        if (w.ngates > 1) apply_gate<Real, WB>(v, w.kind[1], w.l[1], m1);
+        window_gates<Real, WB>(v, w, wg);
 #pragma unroll
         for (int m = 0; m < (1 << WB); ++m) lds[bw_phys(base + (m << w.b))] = v[m];
       }
@@ -238,11 +252,7 @@ __global__ void __launch_bounds__(1 << TB)
       C x = lds[bw_phys(j)];
       if (a.flags & BW_ROT) x = cmul(x, rot);
       if constexpr (PSI) {
-        C p;
-        if constexpr (PSI_PF)
-          p = ps[i];
-        else
-          p = psi[tm.g(j)];
+        const C p = psi[tm.g(j)];
         x = (a.flags & BW_PSI_COEF) ? cfma(p, pc, x) : cadd(x, p);
       }
       xout[tm.g(j)] = x;
@@ -254,10 +264,12 @@ __global__ void __launch_bounds__(1 << TB)
   }
 }
 
+size_t bw_lds_bytes(int n, size_t elem) { return size_t((1 << n) + (1 << (n - 4 > 0 ? n - 4 : 0)) + 1) * elem; }
+
 template <typename Real, int WB, int TB, int NB, bool PSI>
 hipError_t launch_bw_pipe(const BwPassArgs& a, unsigned ntiles, hipStream_t s) {
   static int wgs_per_pass = 0;  // resident workgroups per pass (CUs x workgroups per CU)
-  const size_t shmem = size_t((1 << NB) + (1 << (NB - 4)) + 1) * sizeof(cpx<Real>);
+  const size_t shmem = bw_lds_bytes(NB, sizeof(cpx<Real>));
   auto kern = bw_pipe_kernel<Real, WB, TB, NB, PSI>;
   if (wgs_per_pass == 0) {
     if (shmem > 65536) {
@@ -275,29 +287,28 @@ hipError_t launch_bw_pipe(const BwPassArgs& a, unsigned ntiles, hipStream_t s) {
   }
   const unsigned grid = std::min<unsigned>(ntiles, static_cast<unsigned>(wgs_per_pass));
   hipLaunchKernelGGL(kern, dim3(grid), dim3(1 << TB), shmem, s, a, ntiles, static_cast<const cpx<Real>*>(a.mats),
-                     a.wins, static_cast<cpx<Real>*>(a.xout));
+                     a.wins, a.gates, static_cast<cpx<Real>*>(a.xout));
   return hipGetLastError();
 }
 
 template <typename Real, int WB, int TB>
 hipError_t launch_bw_t(const BwPassArgs& a, unsigned ntiles, hipStream_t s) {
-  const size_t shmem = size_t((1 << a.n) + (1 << (a.n - 4 > 0 ? a.n - 4 : 0)) + 1) * sizeof(cpx<Real>);
+  const size_t shmem = bw_lds_bytes(a.n, sizeof(cpx<Real>));
   auto kern = bw_pass_kernel<Real, WB, TB>;
   if (shmem > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(kern, dim3(ntiles), dim3(1 << TB), shmem, s, a);
+  hipLaunchKernelGGL(kern, dim3(ntiles), dim3(1 << TB), shmem, s, a, static_cast<const cpx<Real>*>(a.mats), a.wins,
+                     a.gates);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t bw_launch_pass(const BwPassArgs& a, bool c64_dt, int wb, unsigned ntiles, hipStream_t s) {
-  // complex64: 512 threads for large tiles; complex128 keeps 256 (register budget)
   if (c64_dt) {
-    const bool big = a.n >= 12;
     // pipelined persistent form when every workgroup gets several tiles
     if (wb == 4 && ntiles >= 1024 && ntiles % 8 == 0 && (a.n == 13 || a.n == 14)) {
       const bool ps = (a.flags & BW_ADD_PSI) != 0;
@@ -305,11 +316,13 @@ hipError_t bw_launch_pass(const BwPassArgs& a, bool c64_dt, int wb, unsigned nti
         return ps ? launch_bw_pipe<float, 4, 9, 13, true>(a, ntiles, s) : launch_bw_pipe<float, 4, 9, 13, false>(a, ntiles, s);
       return ps ? launch_bw_pipe<float, 4, 9, 14, true>(a, ntiles, s) : launch_bw_pipe<float, 4, 9, 14, false>(a, ntiles, s);
     }
-    if (wb == 4) return big ? launch_bw_t<float, 4, 9>(a, ntiles, s) : launch_bw_t<float, 4, 8>(a, ntiles, s);
+    if (wb == 4) return a.n >= 12 ? launch_bw_t<float, 4, 9>(a, ntiles, s) : launch_bw_t<float, 4, 8>(a, ntiles, s);
     if (wb == 3) return launch_bw_t<float, 3, 8>(a, ntiles, s);
     if (wb == 2) return launch_bw_t<float, 2, 8>(a, ntiles, s);
   } else {
-    if (wb == 4) return launch_bw_t<double, 4, 8>(a, ntiles, s);
+    // complex128: 2^13-amplitude tiles (128 KB of LDS, one workgroup per CU)
+    // take 512 threads (the pipelined form would spill registers)
+    if (wb == 4) return a.n >= 13 ? launch_bw_t<double, 4, 9>(a, ntiles, s) : launch_bw_t<double, 4, 8>(a, ntiles, s);
     if (wb == 3) return launch_bw_t<double, 3, 8>(a, ntiles, s);
     if (wb == 2) return launch_bw_t<double, 2, 8>(a, ntiles, s);
   }
@@ -345,25 +358,60 @@ void layout(int L, std::vector<std::vector<int>>* lb, std::vector<std::vector<in
   }
 }
 
-// Windows of up to wb consecutive tile bits covering the gates of one layer.
-// gates: (tile low bit q, width, mat)
-void pack_windows(std::vector<std::array<int, 3>> gates, int n, int wb, std::vector<BwWindow>* out) {
-  std::sort(gates.begin(), gates.end());
-  size_t i = 0;
-  while (i < gates.size()) {
-    const int q0 = gates[i][0];
-    const int b = std::max(0, std::min(q0, n - wb));
-    BwWindow w{};
-    w.b = static_cast<int8_t>(b);
-    w.ngates = 0;
-    while (i < gates.size() && gates[i][0] + gates[i][1] <= b + wb && w.ngates < 2) {
-      w.kind[w.ngates] = static_cast<int8_t>(gates[i][1]);
-      w.l[w.ngates] = static_cast<int8_t>(gates[i][0] - b);
-      w.mat[w.ngates] = static_cast<int16_t>(gates[i][2]);
-      ++w.ngates;
-      ++i;
+// A gate of one pass: tile low bit q, width 1 or 2, matrix index.  Gates are
+// listed in program order (the layer acting first, then the second).
+struct PGate {
+  int q, width, mat;
+};
+
+// Windows of wb consecutive tile bits covering all gates of a pass.  A window
+// takes, in program order, every remaining gate inside it whose earlier
+// gates on shared bits are already applied (in earlier windows or earlier in
+// this one); gates on disjoint bits commute, so this reproduces the program.
+// The window starts at the first remaining gate's low bit or up to wb - 2
+// bits below it, whichever placement applies the most gates.
+void schedule_windows(const std::vector<PGate>& g, int n, int wb, std::vector<BwWin>* wins,
+                      std::vector<BwGate>* out) {
+  constexpr size_t kMaxGates = 2;  // per window (the kernels hold two matrices)
+  const size_t G = g.size();
+  std::vector<char> done(G, 0);
+  auto overlaps = [&](size_t i, size_t j) { return g[i].q < g[j].q + g[j].width && g[j].q < g[i].q + g[i].width; };
+  auto pick = [&](int b, std::vector<size_t>* sel) {
+    std::vector<char> d = done;
+    sel->clear();
+    for (size_t j = 0; j < G && sel->size() < kMaxGates; ++j) {
+      if (d[j] || g[j].q < b || g[j].q + g[j].width > b + wb) continue;
+      bool ready = true;
+      for (size_t i = 0; i < j && ready; ++i)
+        if (!d[i] && overlaps(i, j)) ready = false;
+      if (ready) {
+        d[j] = 1;
+        sel->push_back(j);
+      }
     }
-    out->push_back(w);
+  };
+  size_t left = G;
+  while (left > 0) {
+    size_t f = 0;
+    while (done[f]) ++f;
+    std::vector<size_t> best, cur;
+    int bb = 0;
+    for (int dq = 0; dq == 0 || dq < wb - 1; ++dq) {
+      const int b = std::max(0, std::min(g[f].q - dq, n - wb));
+      pick(b, &cur);
+      if (cur.size() > best.size()) {
+        best = cur;
+        bb = b;
+      }
+    }
+    wins->push_back(BwWin{static_cast<int16_t>(bb), static_cast<int16_t>(out->size()),
+                          static_cast<int16_t>(best.size()), 0});
+    for (size_t j : best) {
+      out->push_back(BwGate{static_cast<int8_t>(g[j].width), static_cast<int8_t>(g[j].q - bb),
+                            static_cast<int16_t>(g[j].mat)});
+      done[j] = 1;
+      --left;
+    }
   }
 }
 
@@ -374,7 +422,8 @@ struct BwProgram {
   struct Pass {
     int n, c, p, wb;
     unsigned ntiles;
-    BwWindow* wins = nullptr;
+    BwWin* wins = nullptr;
+    BwGate* gates = nullptr;
     int nwin = 0;
   };
   int npass = 0;
@@ -383,7 +432,10 @@ struct BwProgram {
   bool c64 = true;
 
   ~BwProgram() {
-    for (Pass& p : pass) (void)hipFree(p.wins);
+    for (Pass& p : pass) {
+      (void)hipFree(p.wins);
+      (void)hipFree(p.gates);
+    }
     (void)hipFree(mats);
   }
 };
@@ -425,25 +477,37 @@ fq_status build_program(floquet_op* op, bool c64_dt, std::shared_ptr<BwProgram>*
   }
 
   const int nmax = c64_dt ? 13 : 12;
-  auto tile_bit_lo = [&](int site) { return L - site; };  // right/single pass: identity
+  // window width: 4 bits (16 amplitudes per thread); 5-bit windows with all
+  // fitting gates cover a 13-bit block in 3 instead of 7 windows but raise
+  // register use so much that the pass gets slower (392 against 377 us at
+  // L = 24)
+  auto window_bits = [&](int n) { return std::min(4, n); };
+  auto upload = [&](BwProgram::Pass& ps, const std::vector<PGate>& g) -> fq_status {
+    std::vector<BwWin> wins;
+    std::vector<BwGate> gl;
+    schedule_windows(g, ps.n, ps.wb, &wins, &gl);
+    ps.nwin = static_cast<int>(wins.size());
+    FQ_HIP_CHECK(hipMalloc(&ps.wins, std::max<size_t>(1, wins.size()) * sizeof(BwWin)));
+    FQ_HIP_CHECK(hipMalloc(&ps.gates, std::max<size_t>(1, gl.size()) * sizeof(BwGate)));
+    if (!wins.empty()) {
+      FQ_HIP_CHECK(hipMemcpy(ps.wins, wins.data(), wins.size() * sizeof(BwWin), hipMemcpyHostToDevice));
+      FQ_HIP_CHECK(hipMemcpy(ps.gates, gl.data(), gl.size() * sizeof(BwGate), hipMemcpyHostToDevice));
+    }
+    return FQ_OK;
+  };
   if (L <= nmax) {
     prog->npass = 1;
     BwProgram::Pass& ps = prog->pass[0];
     ps.n = L;
     ps.c = L;
     ps.p = L;
-    ps.wb = std::min(4, L);
+    ps.wb = window_bits(L);
     ps.ntiles = 1;
-    std::vector<BwWindow> wins;
-    for (int layer = 0; layer < 2; ++layer) {
-      std::vector<std::array<int, 3>> g;
-      for (const GateRef& r : layer == 0 ? refs_b : refs_a)
-        g.push_back({tile_bit_lo(r.site + r.width - 1), r.width, r.mat});
-      pack_windows(g, ps.n, ps.wb, &wins);
-    }
-    ps.nwin = static_cast<int>(wins.size());
-    FQ_HIP_CHECK(hipMalloc(&ps.wins, wins.size() * sizeof(BwWindow)));
-    FQ_HIP_CHECK(hipMemcpy(ps.wins, wins.data(), wins.size() * sizeof(BwWindow), hipMemcpyHostToDevice));
+    std::vector<PGate> g;
+    for (int layer = 0; layer < 2; ++layer)
+      for (const GateRef& r : layer == 0 ? refs_b : refs_a) g.push_back({L - (r.site + r.width - 1), r.width, r.mat});
+    fq_status st = upload(ps, g);
+    if (st != FQ_OK) return st;
   } else {
     // choose the even cut site c_s and chunk c so both tiles fit in LDS
     // (<= 14 bits complex64, <= 13 bits complex128), balancing the two tiles
@@ -471,20 +535,19 @@ fq_status build_program(floquet_op* op, bool c64_dt, std::shared_ptr<BwProgram>*
     pr.n = L - cs + 1;
     pr.c = pr.n;
     pr.p = pr.n;
-    pr.wb = 4;
+    pr.wb = window_bits(pr.n);
     pr.ntiles = 1u << (L - pr.n);
     // left block: sites 1..cs -> global bits [L-cs, L); tile bit = c + (gbit - (L-cs))
     BwProgram::Pass& pl = prog->pass[1];
     pl.n = cs + c;
     pl.c = c;
     pl.p = L - cs;
-    pl.wb = 4;
+    pl.wb = window_bits(pl.n);
     pl.ntiles = 1u << (L - pl.n);
     for (int which = 0; which < 2; ++which) {
       BwProgram::Pass& ps = prog->pass[which];
-      std::vector<BwWindow> wins;
+      std::vector<PGate> g;
       for (int layer = 0; layer < 2; ++layer) {
-        std::vector<std::array<int, 3>> g;
         for (const GateRef& r : layer == 0 ? refs_b : refs_a) {
           const int first = r.site, last = r.site + r.width - 1;
           // right block: U_b's gates starting at c_s or later, U_a's gates
@@ -494,22 +557,15 @@ fq_status build_program(floquet_op* op, bool c64_dt, std::shared_ptr<BwProgram>*
           if (!mine) continue;
           const int gbit_lo = L - last;  // global bit of the gate's last (low) site
           const int tbit = which == 0 ? gbit_lo : c + (gbit_lo - pl.p);
+          if (which == 1 && tbit < c) {
+            set_error("internal: brickwork gate in the chunk bits");
+            return FQ_EINVAL;
+          }
           g.push_back({tbit, r.width, r.mat});
         }
-        if (!g.empty()) {
-          if (which == 1)
-            for (auto& e : g)
-              if (e[0] < c) {
-                set_error("internal: brickwork gate in the chunk bits");
-                return FQ_EINVAL;
-              }
-          pack_windows(g, ps.n, ps.wb, &wins);
-        }
       }
-      ps.nwin = static_cast<int>(wins.size());
-      FQ_HIP_CHECK(hipMalloc(&ps.wins, std::max<size_t>(1, wins.size()) * sizeof(BwWindow)));
-      if (!wins.empty())
-        FQ_HIP_CHECK(hipMemcpy(ps.wins, wins.data(), wins.size() * sizeof(BwWindow), hipMemcpyHostToDevice));
+      fq_status st = upload(ps, g);
+      if (st != FQ_OK) return st;
     }
   }
   *out = prog;
@@ -525,6 +581,7 @@ fq_status run_pass(const BwProgram& prog, int which, const void* in, void* out, 
   a.psi = psi;
   a.mats = prog.mats;
   a.wins = ps.wins;
+  a.gates = ps.gates;
   a.nwin = ps.nwin;
   a.n = ps.n;
   a.c = ps.c;
