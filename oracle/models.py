@@ -22,6 +22,13 @@ Brickwork random circuit (Sec. 2, Eq. (U), Eq. (unitary)):
 
 U_b acting first.  Each layer covers every site exactly once, so each layer is
 one Kronecker product of its gates in site order.
+
+General local circuit (the method applies to any local U, Sec. 2): gates on
+one site or on a nearest-neighbour pair, in the order they act,
+
+    U = G_{n-1} ... G_1 G_0,   G = 1_{2^(i-1)} (x) u (x) 1_{2^(L-i-w+1)},
+
+each embedded by Kronecker products at its first site i (width w).
 """
 
 from __future__ import annotations
@@ -40,6 +47,9 @@ __all__ = [
     "bw_gate_list",
     "bw_dense",
     "bw_apply",
+    "circuit_gate_list",
+    "circuit_dense",
+    "circuit_apply",
     "dense",
     "matvec",
 ]
@@ -141,13 +151,58 @@ def bw_apply(p, psi: np.ndarray) -> np.ndarray:
     return x.reshape(-1)
 
 
+def circuit_gate_list(p) -> List[Tuple[int, int, np.ndarray]]:
+    """Unpack a general circuit into (first site, width, matrix) in acting order."""
+    flat = np.asarray(p.gates, dtype=np.complex128)
+    out = []
+    pos = 0
+    for i, w in zip(p.sites, p.widths):
+        i, w = int(i), int(w)
+        if w not in (1, 2) or i < 1 or i + w - 1 > p.L:
+            raise ValueError(f"bad gate at site {i}, width {w}")
+        n = 2 ** w
+        out.append((i, w, flat[pos:pos + n * n].reshape(n, n)))
+        pos += n * n
+    if pos != flat.size:
+        raise ValueError("gate array has the wrong length")
+    return out
+
+
+def circuit_dense(p) -> np.ndarray:
+    """Dense U: the product of every embedded gate, the first acting first."""
+    L = p.L
+    if L > DENSE_MAX_L:
+        raise ValueError(f"dense U limited to L <= {DENSE_MAX_L}")
+    U = np.eye(2 ** L, dtype=np.complex128)
+    for i, w, u in circuit_gate_list(p):
+        G = np.kron(np.kron(np.eye(2 ** (i - 1)), u), np.eye(2 ** (L - i - w + 1)))
+        U = G @ U
+    return U
+
+
+def circuit_apply(p, psi: np.ndarray) -> np.ndarray:
+    """Matrix-free U psi: every gate in acting order."""
+    L = p.L
+    x = np.asarray(psi, dtype=np.complex128)
+    for i, w, u in circuit_gate_list(p):
+        x = x.reshape(2 ** (i - 1), 2 ** w, 2 ** (L - i - w + 1))
+        x = np.einsum("ab,xbz->xaz", u, x)
+    return x.reshape(-1)
+
+
 def dense(p) -> np.ndarray:
-    """Dense U of either model."""
-    return ki_dense(p) if hasattr(p, "J") else bw_dense(p)
+    """Dense U of any model."""
+    if hasattr(p, "J"):
+        return ki_dense(p)
+    if hasattr(p, "sites"):
+        return circuit_dense(p)
+    return bw_dense(p)
 
 
 def matvec(p) -> Callable[[np.ndarray], np.ndarray]:
-    """Matrix-free U of either model, as a callable."""
+    """Matrix-free U of any model, as a callable."""
     if hasattr(p, "J"):
         return lambda v: ki_apply(p, v)
+    if hasattr(p, "sites"):
+        return lambda v: circuit_apply(p, v)
     return lambda v: bw_apply(p, v)

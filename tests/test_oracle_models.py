@@ -11,7 +11,7 @@ import pytest
 
 from conftest import load_golden
 from oracle import models
-from workloads import (KickedIsingParams, brickwork, brickwork_from_matrices,
+from workloads import (CircuitParams, circuit, circuit_from_brickwork, KickedIsingParams, brickwork, brickwork_from_matrices,
                        kicked_ising)
 
 
@@ -191,3 +191,63 @@ def test_bw_layer_swap_keeps_spectrum():
     Ua, Ub = layer(la), layer(lb)
     _match_spectra(np.linalg.eigvals(Ua @ Ub), np.linalg.eigvals(Ub @ Ua), 1e-10)
     assert np.allclose(models.bw_dense(p), Ua @ Ub, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# General local circuits
+# ---------------------------------------------------------------------------
+
+def _circ(L, gates):
+    """CircuitParams from a list of (site, matrix) in acting order."""
+    sites = [s for s, _ in gates]
+    widths = [1 if np.asarray(m).shape == (2, 2) else 2 for _, m in gates]
+    flat = np.concatenate([np.asarray(m, dtype=np.complex128).reshape(-1) for _, m in gates])
+    return CircuitParams(L=L, sites=np.array(sites), widths=np.array(widths), gates=flat, phi=0.0)
+
+
+X2 = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+CNOT = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0]], dtype=np.complex128)
+
+
+@pytest.mark.parametrize("gates,expect", [
+    # X on site 1 (the most significant bit) then CNOT controlled by site 1: |00> -> |10> -> |11>
+    ([(1, X2), (1, CNOT)], 3),
+    # the same gates in the other order: |00> -> |00> -> |10>
+    ([(1, CNOT), (1, X2)], 2),
+    # X on site 2 then CNOT (control site 1 is 0): |00> -> |01>
+    ([(2, X2), (1, CNOT)], 1),
+])
+def test_circuit_order_hand_examples(gates, expect):
+    p = _circ(2, gates)
+    psi = np.zeros(4, dtype=np.complex128)
+    psi[0] = 1
+    for out in (models.circuit_dense(p) @ psi, models.circuit_apply(p, psi)):
+        assert np.argmax(np.abs(out)) == expect and abs(abs(out[expect]) - 1) < 1e-15
+
+
+@pytest.mark.parametrize("L", [5, 8])
+def test_circuit_of_brickwork_layout_is_brickwork(L):
+    # the brickwork written as a general gate list gives the same U exactly
+    p = brickwork(L, 600 + L)
+    Ub = models.bw_dense(p)
+    Uc = models.circuit_dense(circuit_from_brickwork(p))
+    assert np.max(np.abs(Ub - Uc)) < 1e-13
+
+
+@pytest.mark.parametrize("L", [4, 7])
+def test_circuit_unitary_and_matrix_free(L):
+    p = circuit(L, 700 + L, depth=3)
+    U = models.circuit_dense(p)
+    assert np.max(np.abs(U.conj().T @ U - np.eye(2 ** L))) < 1e-12
+    psi = np.random.default_rng(1).standard_normal(2 ** L) + 0j
+    assert np.max(np.abs(U @ psi - models.circuit_apply(p, psi))) < 1e-12
+
+
+def test_circuit_layers_commute_when_disjoint():
+    # gates on disjoint sites commute: swapping them inside the list keeps U
+    rng = np.random.default_rng(5)
+    a = np.linalg.qr(rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4)))[0]
+    b = np.linalg.qr(rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4)))[0]
+    U1 = models.circuit_dense(_circ(5, [(1, a), (3, b)]))
+    U2 = models.circuit_dense(_circ(5, [(3, b), (1, a)]))
+    assert np.max(np.abs(U1 - U2)) < 1e-14

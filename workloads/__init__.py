@@ -33,6 +33,9 @@ import numpy as np
 __all__ = [
     "KickedIsingParams",
     "BrickworkParams",
+    "CircuitParams",
+    "circuit",
+    "circuit_from_brickwork",
     "kicked_ising",
     "brickwork",
     "brickwork_layout",
@@ -54,6 +57,19 @@ class KickedIsingParams:
     g: float       # transverse kick angle
     periodic: bool
     phi: float     # target phase (only used by the filter / eigensolver)
+
+
+@dataclasses.dataclass
+class CircuitParams:
+    """A general local Floquet circuit: gates in the order they act (first
+    acts first), each on one site or on the nearest-neighbour pair
+    (site, site+1); ``gates`` holds their row-major matrices back to back
+    (4 or 16 complex128 entries; two-site local index 2*b_i + b_{i+1})."""
+    L: int
+    sites: np.ndarray   # (G,) int, first site (1-based)
+    widths: np.ndarray  # (G,) int, 1 or 2
+    gates: np.ndarray   # flat complex128
+    phi: float
 
 
 @dataclasses.dataclass
@@ -134,6 +150,43 @@ def brickwork_cz(L: int, seed: int, *, phi: float = 0.0) -> BrickworkParams:
             r1, r2 = haar_unitary(2, rng), haar_unitary(2, rng)
             mats.append(cz @ np.kron(r1, r2))
     return brickwork_from_matrices(L, mats, phi)
+
+
+def circuit(L: int, seed: int, *, depth: int = 3, phi: float = 0.0) -> CircuitParams:
+    """A local circuit of ``depth`` layers that is not a brickwork: layer t
+    puts Haar-random two-site gates on the bonds (i, i+1) with i = t+1 (mod 3)
+    and a Haar-random one-site gate on every site left free; the layers act
+    in order t = 0, 1, ...  (gates within a layer listed from site 1 up)."""
+    if L < 3:
+        raise ValueError("circuit needs L >= 3")
+    rng = np.random.default_rng(seed)
+    sites, widths, mats = [], [], []
+    for t in range(depth):
+        covered = set()
+        layer = []
+        for i in range(1, L):
+            if (i - 1) % 3 == t % 3:
+                layer.append((i, 2))
+                covered.update((i, i + 1))
+        for i in range(1, L + 1):
+            if i not in covered:
+                layer.append((i, 1))
+        layer.sort()
+        for i, w in layer:
+            sites.append(i)
+            widths.append(w)
+            mats.append(haar_unitary(2 ** w, rng).reshape(-1))
+    return CircuitParams(L=L, sites=np.array(sites, dtype=np.int32), widths=np.array(widths, dtype=np.int32),
+                         gates=np.concatenate(mats).astype(np.complex128), phi=float(phi))
+
+
+def circuit_from_brickwork(p: BrickworkParams) -> CircuitParams:
+    """The brickwork circuit written as a general gate list (U_b first)."""
+    layer_b, layer_a = brickwork_layout(p.L)
+    sites = [s[0] for s in layer_b + layer_a]
+    widths = [len(s) for s in layer_b + layer_a]
+    return CircuitParams(L=p.L, sites=np.array(sites, dtype=np.int32), widths=np.array(widths, dtype=np.int32),
+                         gates=np.asarray(p.gates, dtype=np.complex128).copy(), phi=p.phi)
 
 
 def brickwork_from_matrices(L: int, mats: Sequence[np.ndarray], phi: float = 0.0) -> BrickworkParams:
