@@ -44,7 +44,7 @@ typedef enum {
 
 typedef enum { FQ_C64 = 0, FQ_C128 = 1 } fq_dtype;
 
-typedef enum { FQ_KICKED_ISING = 0, FQ_BRICKWORK = 1 } fq_model;
+typedef enum { FQ_KICKED_ISING = 0, FQ_BRICKWORK = 1, FQ_CIRCUIT = 2 } fq_model;
 
 /*
  * Model description (host memory, copied by create_floquet_op).
@@ -65,6 +65,16 @@ typedef enum { FQ_KICKED_ISING = 0, FQ_BRICKWORK = 1 } fq_model;
  *   Two-site gates are row-major 4x4 with local index 2 b_i + b_{i+1};
  *   one-site gates are row-major 2x2.  J, h must be NULL.
  *
+ * FQ_CIRCUIT: any local Floquet circuit (the method needs only a local U,
+ *   Sec. 2): n_gates gates in the order they act, gate q on the sites
+ *   gate_sites[q] (1-based) .. gate_sites[q] + gate_widths[q] - 1, width 1
+ *   or 2 (nearest neighbours, open chain); gates holds their matrices back to
+ *   back (4 or 16 complex128 entries, same conventions as above).  The U pass
+ *   splits the chain into two blocks along the gates' light cone; a circuit
+ *   whose light cone is too wide for two blocks of <= 14 (complex64) / 13
+ *   (complex128) sites plus a chunk gives FQ_EINVAL (for L > 13).  J, h must
+ *   be NULL.  gate_sites and gate_widths are ignored by the other models.
+ *
  * L must satisfy 2 <= L <= 30.
  */
 typedef struct {
@@ -76,6 +86,8 @@ typedef struct {
   double g;
   const double* gates;
   int n_gates;
+  const int* gate_sites;   /* FQ_CIRCUIT: n_gates first sites (1-based) */
+  const int* gate_widths;  /* FQ_CIRCUIT: n_gates widths (1 or 2) */
 } fq_model_desc;
 
 /* Build an operator: copies the model, builds device phase/gate tables.

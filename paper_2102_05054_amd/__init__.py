@@ -5,5 +5,6 @@ The computation lives in ``libfloquet.so`` (HIP kernels + C ABI, see
 torch tensors for device memory and streams.
 """
 
-from .api import FloquetOp, arnoldi_eigs_batched, brickwork, host_schur, kicked_ising, paper_parameters  # noqa: F401
+from .api import (FloquetOp, arnoldi_eigs_batched, brickwork, circuit, host_schur, kicked_ising,  # noqa: F401
+                  paper_parameters)
 from ._lib import FloquetError, LIB_PATH  # noqa: F401

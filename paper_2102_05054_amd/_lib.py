@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libfloquet.so")
 
 FQ_OK, FQ_NOT_CONVERGED, FQ_EINVAL, FQ_ENOMEM, FQ_EDEVICE, FQ_ENUMERIC = 0, 1, -1, -2, -3, -4
 FQ_C64, FQ_C128 = 0, 1
-FQ_KICKED_ISING, FQ_BRICKWORK = 0, 1
+FQ_KICKED_ISING, FQ_BRICKWORK, FQ_CIRCUIT = 0, 1, 2
 
 STATUS_NAMES = {
     FQ_OK: "FQ_OK", FQ_NOT_CONVERGED: "FQ_NOT_CONVERGED", FQ_EINVAL: "FQ_EINVAL",
@@ -28,6 +28,7 @@ class FqModelDesc(ctypes.Structure):
         ("model", c_int), ("L", c_int), ("periodic", c_int),
         ("J", POINTER(c_double)), ("h", POINTER(c_double)), ("g", c_double),
         ("gates", POINTER(c_double)), ("n_gates", c_int),
+        ("gate_sites", POINTER(c_int)), ("gate_widths", POINTER(c_int)),
     ]
 
 

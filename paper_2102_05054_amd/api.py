@@ -13,10 +13,11 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import _lib
-from ._lib import (FQ_BRICKWORK, FQ_C64, FQ_C128, FQ_KICKED_ISING, FQ_NOT_CONVERGED, FQ_OK,
+from ._lib import (FQ_BRICKWORK, FQ_C64, FQ_C128, FQ_CIRCUIT, FQ_KICKED_ISING, FQ_NOT_CONVERGED, FQ_OK,
                    FqArnoldiOpts, FqArnoldiStats, FqModelDesc, check, lib)
 
-__all__ = ["FloquetOp", "kicked_ising", "brickwork", "arnoldi_eigs_batched", "host_schur", "paper_parameters"]
+__all__ = ["FloquetOp", "kicked_ising", "brickwork", "circuit", "arnoldi_eigs_batched", "host_schur",
+           "paper_parameters"]
 
 
 def _torch():
@@ -189,6 +190,24 @@ def brickwork(L: int, gates) -> FloquetOp:
     desc = FqModelDesc(model=FQ_BRICKWORK, L=int(L), periodic=0, J=None, h=None, g=0.0, gates=ptr,
                        n_gates=int(L) + 1)
     return FloquetOp(desc, keep=(flat,))
+
+
+def circuit(L: int, sites, widths, gates) -> FloquetOp:
+    """General local circuit: gate q acts (in list order) on sites[q] ..
+    sites[q] + widths[q] - 1 (1-based, width 1 or 2) with the row-major
+    matrices packed back to back in ``gates`` (see include/floquet.h)."""
+    sa = np.ascontiguousarray(np.asarray(sites, dtype=np.int32))
+    wa = np.ascontiguousarray(np.asarray(widths, dtype=np.int32))
+    if sa.size != wa.size or sa.size < 1:
+        raise ValueError("sites and widths need one entry per gate")
+    g = np.ascontiguousarray(np.asarray(gates, dtype=np.complex128))
+    if g.size != int(np.sum(np.where(wa == 1, 4, 16))):
+        raise ValueError("gates must hold 4 entries per one-site and 16 per two-site gate")
+    flat, ptr = _dbl_array(np.stack([g.real, g.imag], axis=1).reshape(-1))
+    desc = FqModelDesc(model=FQ_CIRCUIT, L=int(L), periodic=0, J=None, h=None, g=0.0, gates=ptr,
+                       n_gates=int(sa.size), gate_sites=sa.ctypes.data_as(POINTER(ctypes.c_int)),
+                       gate_widths=wa.ctypes.data_as(POINTER(ctypes.c_int)))
+    return FloquetOp(desc, keep=(flat, sa, wa))
 
 
 def arnoldi_eigs_batched(ops: Sequence[FloquetOp], phis: Sequence[float], nev: int, *, k, ncv: int,

@@ -442,29 +442,67 @@ struct BwProgram {
 
 namespace {
 
+// The gates in acting order: the brickwork layout (U_b, then U_a) or a
+// general circuit's list.
+std::vector<GateRef> gate_refs(const floquet_op* op) {
+  std::vector<GateRef> refs;
+  if (op->model == FQ_CIRCUIT) {
+    for (size_t q = 0; q < op->gate_sites.size(); ++q)
+      refs.push_back({op->gate_sites[q], op->gate_widths[q], static_cast<int>(q)});
+    return refs;
+  }
+  std::vector<std::vector<int>> lb, la;
+  layout(op->L, &lb, &la);
+  int mi = 0;
+  for (const auto* lst : {&lb, &la})
+    for (const auto& sites : *lst) refs.push_back({sites[0], static_cast<int>(sites.size()), mi++});
+  return refs;
+}
+
+// Right block of the cut at site cs: in acting order, every gate on sites >= cs
+// whose earlier gates on shared sites are all in the block.  The rest (the
+// left block) then commutes past it, so U = U_left U_right with U_right first.
+// Returns the membership and the largest site a left-block gate touches.
+std::vector<char> right_block(const std::vector<GateRef>& refs, int cs, int* left_max_site) {
+  const size_t G = refs.size();
+  std::vector<char> right(G, 0);
+  *left_max_site = 0;
+  for (size_t j = 0; j < G; ++j) {
+    const int j0 = refs[j].site, j1 = refs[j].site + refs[j].width - 1;
+    bool r = j0 >= cs;
+    for (size_t i = 0; i < j && r; ++i) {
+      const int i0 = refs[i].site, i1 = refs[i].site + refs[i].width - 1;
+      if (!right[i] && i0 <= j1 && j0 <= i1) r = false;
+    }
+    right[j] = r ? 1 : 0;
+    if (!r) *left_max_site = std::max(*left_max_site, j1);
+  }
+  return right;
+}
+
 fq_status build_program(floquet_op* op, bool c64_dt, std::shared_ptr<BwProgram>* out) {
   const int L = op->L;
   auto prog = std::make_shared<BwProgram>();
   prog->c64 = c64_dt;
-  std::vector<std::vector<int>> lb, la;
-  layout(L, &lb, &la);
+  const std::vector<GateRef> refs = gate_refs(op);
   // matrices: each padded to 16 complex (one-site gates use the first 4)
   std::vector<c128> mats;
-  std::vector<GateRef> refs_b, refs_a;
   size_t pos = 0;
-  int mi = 0;
-  for (int layer = 0; layer < 2; ++layer) {
-    const auto& lst = layer == 0 ? lb : la;
-    for (const auto& sites : lst) {
-      const int w = static_cast<int>(sites.size());
-      const int nn = w == 1 ? 4 : 16;
-      for (int e = 0; e < 16; ++e) {
-        const zd z = e < nn ? op->gates[pos + e] : zd(0, 0);
-        mats.push_back(mk<double>(z.real(), z.imag()));
-      }
-      pos += nn;
-      (layer == 0 ? refs_b : refs_a).push_back({sites[0], w, mi++});
+  for (const GateRef& r : refs) {
+    const int nn = r.width == 1 ? 4 : 16;
+    if (pos + nn > op->gates.size()) {
+      set_error("internal: gate matrices shorter than the gate list");
+      return FQ_EINVAL;
     }
+    for (int e = 0; e < 16; ++e) {
+      const zd z = e < nn ? op->gates[pos + e] : zd(0, 0);
+      mats.push_back(mk<double>(z.real(), z.imag()));
+    }
+    pos += nn;
+  }
+  if (mats.size() / 16 > 32767) {
+    set_error("circuit: too many gates for the window descriptors");
+    return FQ_EINVAL;
   }
   if (c64_dt) {
     std::vector<c64> m32(mats.size());
@@ -485,7 +523,7 @@ fq_status build_program(floquet_op* op, bool c64_dt, std::shared_ptr<BwProgram>*
   auto upload = [&](BwProgram::Pass& ps, const std::vector<PGate>& g) -> fq_status {
     std::vector<BwWin> wins;
     std::vector<BwGate> gl;
-    schedule_windows(g, ps.n, ps.wb, &wins, &gl);
+    if (!g.empty()) schedule_windows(g, ps.n, ps.wb, &wins, &gl);
     ps.nwin = static_cast<int>(wins.size());
     FQ_HIP_CHECK(hipMalloc(&ps.wins, std::max<size_t>(1, wins.size()) * sizeof(BwWin)));
     FQ_HIP_CHECK(hipMalloc(&ps.gates, std::max<size_t>(1, gl.size()) * sizeof(BwGate)));
@@ -504,69 +542,70 @@ fq_status build_program(floquet_op* op, bool c64_dt, std::shared_ptr<BwProgram>*
     ps.wb = window_bits(L);
     ps.ntiles = 1;
     std::vector<PGate> g;
-    for (int layer = 0; layer < 2; ++layer)
-      for (const GateRef& r : layer == 0 ? refs_b : refs_a) g.push_back({L - (r.site + r.width - 1), r.width, r.mat});
+    for (const GateRef& r : refs) g.push_back({L - (r.site + r.width - 1), r.width, r.mat});
+    return (upload(ps, g) == FQ_OK) ? (*out = prog, FQ_OK) : FQ_EDEVICE;
+  }
+  // choose the cut site c_s and chunk c so that both tiles fit in LDS (<= 14
+  // bits complex64, <= 13 bits complex128), balancing the two tiles; for the
+  // brickwork this gives an even c_s (the light cone of U_a U_b)
+  const int nfit = c64_dt ? 14 : 13;
+  int best_cs = -1, best_c = 0, best_left = 0;
+  for (int c = c64_dt ? 3 : 2; c >= 1 && best_cs < 0; --c) {
+    int best_span = 1 << 30, best_sum = 1 << 30;
+    for (int cs = 2; cs <= L - 1; ++cs) {
+      int left_max = 0;
+      (void)right_block(refs, cs, &left_max);
+      const int nR = L - cs + 1, nL = std::max(left_max, 1) + c;
+      if (left_max >= L) continue;
+      const int span = std::max(nR, nL), sum = nR + nL;
+      if (nR <= nfit && nL <= nfit && (span < best_span || (span == best_span && sum < best_sum))) {
+        best_span = span;
+        best_sum = sum;
+        best_cs = cs;
+        best_left = std::max(left_max, 1);
+      }
+    }
+    if (best_cs >= 0) best_c = c;
+  }
+  if (best_cs < 0) {
+    set_error("no two-block split of the circuit for L = " + std::to_string(L) +
+              " (light cone too wide for tiles of " + std::to_string(nfit) + " bits)");
+    return FQ_EINVAL;
+  }
+  const int cs = best_cs, c = best_c;
+  int left_max = 0;
+  const std::vector<char> right = right_block(refs, cs, &left_max);
+  prog->npass = 2;
+  // right block: sites cs..L -> global bits [0, L-cs]
+  BwProgram::Pass& pr = prog->pass[0];
+  pr.n = L - cs + 1;
+  pr.c = pr.n;
+  pr.p = pr.n;
+  pr.wb = window_bits(pr.n);
+  pr.ntiles = 1u << (L - pr.n);
+  // left block: sites 1..best_left -> global bits [L-best_left, L); tile bit = c + (gbit - (L-best_left))
+  BwProgram::Pass& pl = prog->pass[1];
+  pl.n = best_left + c;
+  pl.c = c;
+  pl.p = L - best_left;
+  pl.wb = window_bits(pl.n);
+  pl.ntiles = 1u << (L - pl.n);
+  for (int which = 0; which < 2; ++which) {
+    BwProgram::Pass& ps = prog->pass[which];
+    std::vector<PGate> g;
+    for (size_t q = 0; q < refs.size(); ++q) {
+      if ((right[q] != 0) != (which == 0)) continue;
+      const GateRef& r = refs[q];
+      const int gbit_lo = L - (r.site + r.width - 1);  // global bit of the gate's last (low) site
+      const int tbit = which == 0 ? gbit_lo : c + (gbit_lo - pl.p);
+      if (tbit < (which == 0 ? 0 : c) || tbit + r.width > ps.n) {
+        set_error("internal: circuit gate outside its block");
+        return FQ_EINVAL;
+      }
+      g.push_back({tbit, r.width, r.mat});
+    }
     fq_status st = upload(ps, g);
     if (st != FQ_OK) return st;
-  } else {
-    // choose the even cut site c_s and chunk c so both tiles fit in LDS
-    // (<= 14 bits complex64, <= 13 bits complex128), balancing the two tiles
-    const int nfit = c64_dt ? 14 : 13;
-    int best_cs = -1, best_c = 0;
-    for (int c = c64_dt ? 3 : 2; c >= 1 && best_cs < 0; --c) {
-      int best_span = 1 << 30;
-      for (int cs = 4; cs <= L - 3; cs += 2) {
-        const int nR = L - cs + 1, nL = cs + c;
-        if (nR <= nfit && nL <= nfit && std::max(nR, nL) < best_span) {
-          best_span = std::max(nR, nL);
-          best_cs = cs;
-        }
-      }
-      if (best_cs >= 0) best_c = c;
-    }
-    if (best_cs < 0) {
-      set_error("brickwork: no two-tile split for L = " + std::to_string(L));
-      return FQ_EINVAL;
-    }
-    const int cs = best_cs, c = best_c;
-    prog->npass = 2;
-    // right block: sites cs..L -> global bits [0, L-cs]
-    BwProgram::Pass& pr = prog->pass[0];
-    pr.n = L - cs + 1;
-    pr.c = pr.n;
-    pr.p = pr.n;
-    pr.wb = window_bits(pr.n);
-    pr.ntiles = 1u << (L - pr.n);
-    // left block: sites 1..cs -> global bits [L-cs, L); tile bit = c + (gbit - (L-cs))
-    BwProgram::Pass& pl = prog->pass[1];
-    pl.n = cs + c;
-    pl.c = c;
-    pl.p = L - cs;
-    pl.wb = window_bits(pl.n);
-    pl.ntiles = 1u << (L - pl.n);
-    for (int which = 0; which < 2; ++which) {
-      BwProgram::Pass& ps = prog->pass[which];
-      std::vector<PGate> g;
-      for (int layer = 0; layer < 2; ++layer) {
-        for (const GateRef& r : layer == 0 ? refs_b : refs_a) {
-          const int first = r.site, last = r.site + r.width - 1;
-          // right block: U_b's gates starting at c_s or later, U_a's gates
-          // starting right of c_s; everything else is in the left block
-          const bool right = layer == 0 ? first >= cs : first > cs;
-          const bool mine = which == 0 ? right : !right;
-          if (!mine) continue;
-          const int gbit_lo = L - last;  // global bit of the gate's last (low) site
-          const int tbit = which == 0 ? gbit_lo : c + (gbit_lo - pl.p);
-          if (which == 1 && tbit < c) {
-            set_error("internal: brickwork gate in the chunk bits");
-            return FQ_EINVAL;
-          }
-          g.push_back({tbit, r.width, r.mat});
-        }
-      }
-      fq_status st = upload(ps, g);
-      if (st != FQ_OK) return st;
-    }
   }
   *out = prog;
   return FQ_OK;
@@ -602,9 +641,29 @@ fq_status run_pass(const BwProgram& prog, int which, const void* in, void* out, 
 }  // namespace
 
 fq_status bw_create(floquet_op* op) {
-  fq_status st = build_program(op, true, &op->bw32);
-  if (st != FQ_OK) return st;
-  return build_program(op, false, &op->bw64);
+  // a circuit whose light cone fits complex64 tiles but not the smaller
+  // complex128 ones keeps the complex64 program; the complex128 calls then
+  // fail with FQ_EINVAL
+  const fq_status s32 = build_program(op, true, &op->bw32);
+  const std::string e32 = floquet_last_error();
+  const fq_status s64 = build_program(op, false, &op->bw64);
+  const std::string e64 = floquet_last_error();
+  if (s32 != FQ_OK && s32 != FQ_EINVAL) {
+    set_error(e32);
+    return s32;
+  }
+  if (s64 != FQ_OK && s64 != FQ_EINVAL) {
+    set_error(e64);
+    return s64;
+  }
+  if (s32 != FQ_OK && s64 != FQ_OK) {
+    set_error(e32);
+    return FQ_EINVAL;
+  }
+  if (s32 != FQ_OK) op->bw_missing = "complex64: " + e32;
+  if (s64 != FQ_OK) op->bw_missing = "complex128: " + e64;
+  clear_error();
+  return FQ_OK;
 }
 
 void bw_destroy(floquet_op* op) {
@@ -612,8 +671,17 @@ void bw_destroy(floquet_op* op) {
   op->bw64.reset();
 }
 
+// the program of dtype, or nullptr (with the error set) if it could not be built
+const BwProgram* program_for(const floquet_op* op, fq_dtype dt) {
+  const BwProgram* p = dt == FQ_C64 ? op->bw32.get() : op->bw64.get();
+  if (!p) set_error("this circuit has no " + op->bw_missing);
+  return p;
+}
+
 fq_status bw_apply_U(floquet_op* op, fq_dtype dt, const void* psi, void* out, hipStream_t s) {
-  const BwProgram& prog = dt == FQ_C64 ? *op->bw32 : *op->bw64;
+  const BwProgram* pp = program_for(op, dt);
+  if (!pp) return FQ_EINVAL;
+  const BwProgram& prog = *pp;
   const void* in = psi;
   for (int i = 0; i < prog.npass; ++i) {
     fq_status st = run_pass(prog, i, in, out, nullptr, 0, zd(1, 0), zd(1, 0), s);
@@ -627,7 +695,9 @@ fq_status bw_apply_U(floquet_op* op, fq_dtype dt, const void* psi, void* out, hi
 // the geometric sum, 1 for a general polynomial).
 fq_status bw_filter(floquet_op* op, int k, double phi, const zd* coefs, fq_dtype dt, const void* psi, void* out,
                     hipStream_t s) {
-  const BwProgram& prog = dt == FQ_C64 ? *op->bw32 : *op->bw64;
+  const BwProgram* pp = program_for(op, dt);
+  if (!pp) return FQ_EINVAL;
+  const BwProgram& prog = *pp;
   const zd rot = coefs ? zd(1, 0) : std::polar(1.0, -phi);
   const zd a_k = coefs ? coefs[k] : zd(1, 0);
   if (a_k != zd(1, 0)) {

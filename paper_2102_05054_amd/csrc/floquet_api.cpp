@@ -437,7 +437,7 @@ fq_status get_tables(floquet_op* op, double phi, const PhaseTables** out) {
 }
 
 fq_status apply_U_internal(floquet_op* op, fq_dtype dt, const void* psi, void* out, hipStream_t s) {
-  if (op->model == FQ_BRICKWORK) return bw_apply_U(op, dt, psi, out, s);
+  if (op->model != FQ_KICKED_ISING) return bw_apply_U(op, dt, psi, out, s);
   return dt == FQ_C64 ? ki_apply_U<float>(op, psi, out, s) : ki_apply_U<double>(op, psi, out, s);
 }
 
@@ -449,7 +449,7 @@ fq_status filter_internal(floquet_op* op, int k, double phi, const zd* coefs, fq
     FQ_HIP_CHECK(hipMemcpyAsync(out, psi, bytes, hipMemcpyDeviceToDevice, s));
     return FQ_OK;
   }
-  if (op->model == FQ_BRICKWORK) return bw_filter(op, k, phi, coefs, dt, psi, out, s);
+  if (op->model != FQ_KICKED_ISING) return bw_filter(op, k, phi, coefs, dt, psi, out, s);
   return dt == FQ_C64 ? ki_filter<float>(op, k, phi, coefs, psi, out, s)
                       : ki_filter<double>(op, k, phi, coefs, psi, out, s);
 }
@@ -552,6 +552,37 @@ fq_status create_floquet_op(const fq_model_desc* desc, floquet_op** out) {
     const int n_single = 2;
     const int n_pair = L - 1;
     const size_t n_c = size_t(n_pair) * 16 + size_t(n_single) * 4;
+    op->gates.resize(n_c);
+    for (size_t i = 0; i < n_c; ++i) {
+      op->gates[i] = zd(desc->gates[2 * i], desc->gates[2 * i + 1]);
+      if (!std::isfinite(desc->gates[2 * i]) || !std::isfinite(desc->gates[2 * i + 1])) {
+        set_error("gates must be finite");
+        return FQ_EINVAL;
+      }
+    }
+    fq_status st = bw_create(op.get());
+    if (st != FQ_OK) return st;
+  } else if (desc->model == FQ_CIRCUIT) {
+    if (!desc->gates || desc->J || desc->h || !desc->gate_sites || !desc->gate_widths || desc->n_gates < 1) {
+      set_error("circuit needs gates, gate_sites, gate_widths, n_gates >= 1 (and J == h == NULL)");
+      return FQ_EINVAL;
+    }
+    const int L = desc->L;
+    size_t n_c = 0;
+    for (int q = 0; q < desc->n_gates; ++q) {
+      const int i = desc->gate_sites[q], w = desc->gate_widths[q];
+      if ((w != 1 && w != 2) || i < 1 || i + w - 1 > L) {
+        set_error("circuit gate " + std::to_string(q) + ": need width 1 or 2 and sites inside 1..L");
+        return FQ_EINVAL;
+      }
+      op->gate_sites.push_back(i);
+      op->gate_widths.push_back(w);
+      n_c += w == 1 ? 4 : 16;
+    }
+    if (n_c > (size_t(1) << 15) * 16) {
+      set_error("circuit: too many gates");
+      return FQ_EINVAL;
+    }
     op->gates.resize(n_c);
     for (size_t i = 0; i < n_c; ++i) {
       op->gates[i] = zd(desc->gates[2 * i], desc->gates[2 * i + 1]);

@@ -4,6 +4,7 @@
 
 #include <complex>
 #include <memory>
+#include <string>
 #include <vector>
 
 #include "common.h"
@@ -55,7 +56,8 @@ struct floquet_op {
   int periodic;
   std::vector<double> J, h;
   double g = 0.0;
-  std::vector<fq::zd> gates;  // brickwork, flat as given
+  std::vector<fq::zd> gates;  // brickwork / circuit matrices, flat as given
+  std::vector<int> gate_sites, gate_widths;  // circuit: first site and width of each gate
   int device = 0;
 
   // kicked Ising kick form
@@ -68,8 +70,10 @@ struct floquet_op {
   fq::KiPlan plan64, plan128;           // multi-pass plans per dtype
   int single_max_L64 = 10, single_max_L128 = 10;
 
-  // brickwork device programs (one per dtype), owned
+  // brickwork / circuit device programs (one per dtype), owned; a circuit
+  // whose light cone is too wide for one precision's tiles lacks that program
   std::shared_ptr<fq::BwProgram> bw32, bw64;
+  std::string bw_missing;  // why a program is missing
 
   // scratch for the mixed-precision filter and the polynomial coefficients
   void* psi32 = nullptr;

@@ -41,3 +41,8 @@ def rel(a, b):
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
+
+
+def circ_op(p):
+    from paper_2102_05054_amd import circuit
+    return circuit(p.L, p.sites, p.widths, p.gates)
