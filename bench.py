@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--W", type=float, default=1.0)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--max-restarts", type=int, default=60)
+    ap.add_argument("--block", type=int, default=1, help="vectors filtered per Krylov step (1, 2, 4, 8)")
     ap.add_argument("--no-c128", action="store_true", help="skip the complex128 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--roofline-steps", type=int, default=2000)
@@ -394,7 +395,7 @@ def main():
         ev, _, res, st, status = op.arnoldi_eigs(args.nev, 0.0, k=k, ncv=args.ncv, tol=args.tol,
                                                  max_restarts=args.max_restarts, filter_dtype=dtype,
                                                  refine=True, seed=1, want_vectors=False,
-                                                 allow_not_converged=True)
+                                                 allow_not_converged=True, block=args.block)
         torch.cuda.synchronize()
         return time.perf_counter() - t0, ev, res, st, status
 
@@ -415,7 +416,7 @@ def main():
     if not args.no_c128:
         dt2, ev2, res2, st2, status2 = solve("c128")
         c128 = {"time_s": dt2, "status": int(status2), "nconv": st2["nconv"], "max_residual": float(res2.max()),
-                "n_U_apps": st2["n_U_apps"], "n_restarts": st2["n_restarts"]}
+                "n_U_apps": st2["n_U_apps"], "n_restarts": st2["n_restarts"], "t_filter_s": st2["t_filter"]}
 
     roof = filter_roofline(op, L, args.roofline_steps)
     cpu = None if args.no_cpu else cpu_baseline(p)
@@ -436,15 +437,17 @@ def main():
         "data": "synthetic (seeded kicked-Ising couplings)",
         "config": {
             "workload": f"kicked Ising L={L} (d={d}), W={args.W}, nev={args.nev}, ncv={args.ncv}, "
-                        f"k={k} (paper rule 0.8*2^(L+1)/ncv), phi=0, tol={args.tol}",
-            "L": L, "nev": args.nev, "ncv": args.ncv, "k": k, "phi": 0.0,
+                        f"k={k} (paper rule 0.8*2^(L+1)/ncv), phi=0, tol={args.tol}, block={args.block}",
+            "L": L, "nev": args.nev, "ncv": args.ncv, "k": k, "phi": 0.0, "block": args.block,
         },
         "time_to_eigenpairs_s": {"c64+refine": last_dt, "c128": c128["time_s"] if c128 else None},
         "eigenpairs_per_s": {"c64+refine": args.nev / last_dt,
                              "c128": (args.nev / c128["time_s"]) if c128 else None},
         "solve": {"status": int(last_status), "nconv": last_st["nconv"], "max_residual": float(last_res.max()),
                   "n_restarts": last_st["n_restarts"], "n_U_apps": last_st["n_U_apps"],
-                  "n_U_apps_c64": last_st["n_U_apps_c64"], "t_refine_s": last_st["t_refine"]},
+                  "n_U_apps_c64": last_st["n_U_apps_c64"], "t_refine_s": last_st["t_refine"],
+                  "t_filter_s": last_st["t_filter"], "t_orth_s": last_st["t_orth"],
+                  "t_restart_s": last_st["t_restart"]},
         "c128_solve": c128,
         "roofline": {
             "bound": "hbm",

@@ -118,6 +118,21 @@ fq_status apply_filter(floquet_op* op, int k, double phi, fq_dtype dtype,
                        const void* psi_dev, void* out_dev, void* hip_stream);
 
 /*
+ * out_j = g_k(U) psi_j for n_vec vectors at once (Sec. 3, Eq. (geo); the
+ * filter of a block of Krylov vectors, Sec. 4).  psi_dev / out_dev hold n_vec
+ * states of dtype back to back (vector j at offset j*d); out must not overlap
+ * psi.  Kicked-Ising ops (L >= 4, k >= 1) advance all vectors in one launch
+ * per Horner pass (tile shape picked by a timing autotuner on the first call
+ * for each (k, precision, vector-count class), which also writes out); other
+ * ops filter the vectors one after another.  Calls on one op must not run
+ * concurrently on different streams (the op's launch descriptors are shared).
+ * Asynchronous on hip_stream.  FQ_EINVAL for k < 0, non-finite phi, n_vec
+ * outside 1..65535 or overlapping buffers.
+ */
+fq_status apply_filter_many(floquet_op* op, int k, double phi, fq_dtype dtype, int n_vec,
+                            const void* psi_dev, void* out_dev, void* hip_stream);
+
+/*
  * out = sum_{m=0..k} a_m U^m psi, a general polynomial filter (Sec. 3,
  * Eq. (poly)), evaluated by Horner's rule w <- a_{m} psi + U w from w = a_k psi.
  * coeffs_host: k+1 complex128 coefficients a_0..a_k (interleaved re, im).
@@ -142,6 +157,11 @@ typedef struct {
                                 e.g. a damped kernel) instead of the geometric sum; the pairs of
                                 largest |p(omega)| are returned, ordered by arc distance to phi.
                                 NULL: geometric sum.  Needs refine_k = 0 or k. */
+  int block;               /* 0 or 1: single-vector Krylov-Schur.  2, 4 or 8: block Krylov-Schur,
+                              the space grown by this many filtered vectors per step (one batched
+                              filter launch per Horner pass for the block; Sec. 4's method with a
+                              block start space).  Needs floor(ncv / block) * block >= nev + 2 *
+                              block; arnoldi_eigs only (arnoldi_eigs_batched: FQ_EINVAL). */
 } fq_arnoldi_opts;
 
 /* Counters and per-phase wall times (seconds) of one solve. */

@@ -36,7 +36,7 @@ class FqArnoldiOpts(ctypes.Structure):
     _fields_ = [
         ("k", c_int), ("ncv", c_int), ("tol", c_double), ("max_restarts", c_int),
         ("filter_dtype", c_int), ("refine", c_int), ("seed", c_ulonglong), ("v0_dev", c_void_p),
-        ("refine_k", c_int), ("poly_coeffs", POINTER(c_double)),
+        ("refine_k", c_int), ("poly_coeffs", POINTER(c_double)), ("block", c_int),
     ]
 
 
@@ -59,6 +59,7 @@ SIGNATURES = [
     ("floquet_op_dim", c_longlong, [c_void_p]),
     ("apply_U", c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
     ("apply_filter", c_int, [c_void_p, c_int, c_double, c_int, c_void_p, c_void_p, c_void_p]),
+    ("apply_filter_many", c_int, [c_void_p, c_int, c_double, c_int, c_int, c_void_p, c_void_p, c_void_p]),
     ("apply_polynomial", c_int, [c_void_p, c_int, POINTER(c_double), c_int, c_void_p, c_void_p, c_void_p]),
     ("arnoldi_eigs", c_int, [c_void_p, c_int, c_double, POINTER(FqArnoldiOpts), POINTER(c_double), c_void_p,
                              POINTER(c_double), POINTER(FqArnoldiStats), c_void_p]),

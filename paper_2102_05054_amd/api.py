@@ -108,6 +108,18 @@ class FloquetOp:
                                  _stream_ptr(stream)), "apply_filter")
         return out
 
+    def apply_filter_many(self, psi, k: int, phi: float, out=None, stream=None):
+        """out[j] = sum_{n=0..k} (e^{-i phi} U)^n psi[j] for the rows of psi (n_vec x d)."""
+        torch = _torch()
+        if psi.dim() != 2 or psi.shape[1] != self.dim or not psi.is_cuda or not psi.is_contiguous():
+            raise ValueError(f"psi must be a contiguous (n_vec, {self.dim}) device tensor")
+        out = torch.empty_like(psi) if out is None else out
+        if out.shape != psi.shape or out.dtype != psi.dtype or not out.is_cuda or not out.is_contiguous():
+            raise ValueError("out must be a contiguous device tensor of psi's shape and dtype")
+        check(lib().apply_filter_many(self.handle, int(k), float(phi), _dtype_code(psi), int(psi.shape[0]),
+                                      _dptr(psi), _dptr(out), _stream_ptr(stream)), "apply_filter_many")
+        return out
+
     def apply_polynomial(self, psi, coeffs: Sequence[complex], out=None, stream=None):
         """out = sum_m coeffs[m] U^m psi."""
         torch = _torch()
@@ -123,11 +135,12 @@ class FloquetOp:
     def arnoldi_eigs(self, nev: int, phi: float, *, k: int, ncv: int, tol: float = 1e-10,
                      max_restarts: int = 200, filter_dtype: str = "c128", refine: bool = True,
                      seed: int = 0, v0=None, want_vectors: bool = True, stream=None,
-                     allow_not_converged: bool = False, refine_k: int = 0, poly=None):
+                     allow_not_converged: bool = False, refine_k: int = 0, poly=None, block: int = 1):
         """Eigenpairs of U closest to e^{i phi}.  Returns (evals, evecs, resid, stats, status).
 
         ``poly`` (optional): coefficients a_0..a_k of the filter sum_m a_m U^m used
-        instead of the geometric sum (k is then len(poly) - 1)."""
+        instead of the geometric sum (k is then len(poly) - 1).
+        ``block`` (1, 2, 4 or 8): vectors filtered per Krylov step (block Krylov-Schur)."""
         torch = _torch()
         pc = None
         if poly is not None:
@@ -138,7 +151,7 @@ class FloquetOp:
                              filter_dtype=FQ_C64 if filter_dtype == "c64" else FQ_C128,
                              refine=1 if refine else 0, seed=int(seed),
                              v0_dev=c_void_p(v0.data_ptr()) if v0 is not None else None, refine_k=int(refine_k),
-                             poly_coeffs=pcp if pc is not None else None)
+                             poly_coeffs=pcp if pc is not None else None, block=int(block))
         if v0 is not None:
             self._check_state(v0, "v0")
             if v0.dtype != torch.complex128:

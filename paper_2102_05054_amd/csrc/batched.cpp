@@ -785,6 +785,10 @@ fq_status arnoldi_batched_solve(floquet_op* const* ops, int n_ops, const double*
     set_error("arnoldi_eigs_batched: opts.v0_dev must be NULL (each problem uses the seeded start vector)");
     return FQ_EINVAL;
   }
+  if (o->block > 1) {
+    set_error("arnoldi_eigs_batched: opts.block must be 0 or 1 (block Krylov-Schur is for arnoldi_eigs)");
+    return FQ_EINVAL;
+  }
   if (o->poly_coeffs && k_per_op) {
     set_error("arnoldi_eigs_batched: a user polynomial fixes the filter order: k_per_op must be NULL");
     return FQ_EINVAL;

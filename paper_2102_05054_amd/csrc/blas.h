@@ -116,4 +116,13 @@ hipError_t launch_b_basis_gemm(const GemmDesc* g, unsigned n, size_t d, hipStrea
 // Ritz pair i of n problems, after u = U y: omega, residual; y normalised
 hipError_t launch_r_rayleigh(const RDesc* rd, unsigned n, int i, size_t d, hipStream_t s);
 
+// Block forms for b in {1, 2, 4, 8} vectors W[:, c] at W + c*ldw:
+// partial[blk*ldp + i*b + c] = row-block sums of conj(V[r, i]) W[r, c]
+// (reduce with launch_reduce_cols over ncols*b entries);
+hipError_t launch_bdots(const c128* V, size_t ldv, int ncols, const c128* W, size_t ldw, int b, size_t d,
+                        c128* partial, int ldp, hipStream_t s);
+// W[:, c] -= sum_i V[:, i] H[i*b + c]  (H: ncols x b on the device, ncols*b <= 4096)
+hipError_t launch_bupdate(const c128* V, size_t ldv, int ncols, const c128* H, c128* W, size_t ldw, int b, size_t d,
+                          hipStream_t s);
+
 }  // namespace fq

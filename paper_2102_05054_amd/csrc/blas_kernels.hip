@@ -637,6 +637,101 @@ __global__ void __launch_bounds__(NT) r_reduce_rn_kernel(const RDesc* rd, int i,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Block forms (block Krylov-Schur): b vectors W[:, c] = W + c*ldw at once, so
+// that V is read once for the whole block.
+// ---------------------------------------------------------------------------
+// partial[blk*ldp + i*B + c] = sum over the block's rows of conj(V[r, i]) W[r, c]
+template <int B>
+__global__ void __launch_bounds__(NT) bdots_kernel(const c128* __restrict__ V, size_t ldv, int ncols,
+                                                   const c128* __restrict__ W, size_t ldw, size_t d,
+                                                   c128* __restrict__ partial, int ldp) {
+  constexpr int NCB = NCH / B > 0 ? NCH / B : 1;  // V columns per reduction round
+  __shared__ double red[NT / 64][2 * NCH];
+  const int tid = threadIdx.x;
+  const size_t r0 = static_cast<size_t>(blockIdx.x) * NT * RPT + tid;
+  c128 wr[RPT][B];
+  bool ok[RPT];
+#pragma unroll
+  for (int t = 0; t < RPT; ++t) {
+    const size_t r = r0 + size_t(t) * NT;
+    ok[t] = r < d;
+#pragma unroll
+    for (int c = 0; c < B; ++c) wr[t][c] = ok[t] ? W[size_t(c) * ldw + r] : mk<double>(0, 0);
+  }
+  for (int i0 = 0; i0 < ncols; i0 += NCB) {
+    double ax[NCH], ay[NCH];
+#pragma unroll
+    for (int q = 0; q < NCH; ++q) ax[q] = ay[q] = 0.0;
+#pragma unroll
+    for (int u = 0; u < NCB; ++u) {
+      if (i0 + u < ncols) {
+        const c128* col = V + size_t(i0 + u) * ldv;
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) {
+          if (ok[t]) {
+            const c128 v = col[r0 + size_t(t) * NT];
+#pragma unroll
+            for (int c = 0; c < B; ++c) {
+              ax[u * B + c] += v.x * wr[t][c].x + v.y * wr[t][c].y;
+              ay[u * B + c] += v.x * wr[t][c].y - v.y * wr[t][c].x;
+            }
+          }
+        }
+      }
+    }
+    block_sum_nch(ax, ay, red, tid);
+    if (tid < NCB * B && i0 + tid / B < ncols) {
+      double sx = 0.0, sy = 0.0;
+#pragma unroll
+      for (int q = 0; q < NT / 64; ++q) {
+        sx += red[q][2 * tid];
+        sy += red[q][2 * tid + 1];
+      }
+      partial[size_t(blockIdx.x) * ldp + size_t(i0) * B + tid] = mk<double>(sx, sy);
+    }
+    __syncthreads();
+  }
+}
+
+// W[:, c] -= sum_{i < ncols} V[:, i] H[i*B + c]   (H on the device)
+template <int B>
+__global__ void __launch_bounds__(NT) bupdate_kernel(const c128* __restrict__ V, size_t ldv, int ncols,
+                                                     const c128* __restrict__ H, c128* __restrict__ W, size_t ldw,
+                                                     size_t d) {
+  extern __shared__ c128 hs[];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < ncols * B; i += NT) hs[i] = H[i];
+  __syncthreads();
+  const size_t r0 = static_cast<size_t>(blockIdx.x) * NT * RPT + tid;
+  c128 acc[RPT][B];
+  bool ok[RPT];
+#pragma unroll
+  for (int t = 0; t < RPT; ++t) {
+    const size_t r = r0 + size_t(t) * NT;
+    ok[t] = r < d;
+#pragma unroll
+    for (int c = 0; c < B; ++c) acc[t][c] = ok[t] ? W[size_t(c) * ldw + r] : mk<double>(0, 0);
+  }
+  for (int i = 0; i < ncols; ++i) {
+    c128 v[RPT];
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) v[t] = ok[t] ? V[size_t(i) * ldv + r0 + size_t(t) * NT] : mk<double>(0, 0);
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      const c128 hh = hs[i * B + c];
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) acc[t][c] = csub(acc[t][c], cmul(v[t], hh));
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < RPT; ++t)
+    if (ok[t]) {
+#pragma unroll
+      for (int c = 0; c < B; ++c) W[size_t(c) * ldw + r0 + size_t(t) * NT] = acc[t][c];
+    }
+}
+
 __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
   x += 0x9E3779B97F4A7C15ull;
   x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -841,6 +936,34 @@ hipError_t launch_r_rayleigh(const RDesc* rd, unsigned n, int i, size_t d, hipSt
   hipLaunchKernelGGL(r_reduce2_kernel, dim3(1, n), dim3(NT), 0, s, rd, i, nblk);
   hipLaunchKernelGGL(r_axpy_norm_kernel, dim3(nblk, n), dim3(NT), 0, s, rd, i, d);
   hipLaunchKernelGGL(r_reduce_rn_kernel, dim3(1, n), dim3(NT), 0, s, rd, i, nblk);
+  return hipGetLastError();
+}
+
+hipError_t launch_bdots(const c128* V, size_t ldv, int ncols, const c128* W, size_t ldw, int b, size_t d,
+                        c128* partial, int ldp, hipStream_t s) {
+  const dim3 grid(row_blocks(d));
+  switch (b) {
+    case 1: hipLaunchKernelGGL(bdots_kernel<1>, grid, dim3(NT), 0, s, V, ldv, ncols, W, ldw, d, partial, ldp); break;
+    case 2: hipLaunchKernelGGL(bdots_kernel<2>, grid, dim3(NT), 0, s, V, ldv, ncols, W, ldw, d, partial, ldp); break;
+    case 4: hipLaunchKernelGGL(bdots_kernel<4>, grid, dim3(NT), 0, s, V, ldv, ncols, W, ldw, d, partial, ldp); break;
+    case 8: hipLaunchKernelGGL(bdots_kernel<8>, grid, dim3(NT), 0, s, V, ldv, ncols, W, ldw, d, partial, ldp); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_bupdate(const c128* V, size_t ldv, int ncols, const c128* H, c128* W, size_t ldw, int b, size_t d,
+                          hipStream_t s) {
+  const dim3 grid(row_blocks(d));
+  const size_t sh = sizeof(c128) * size_t(ncols) * b;
+  if (sh > 65536) return hipErrorInvalidValue;
+  switch (b) {
+    case 1: hipLaunchKernelGGL(bupdate_kernel<1>, grid, dim3(NT), sh, s, V, ldv, ncols, H, W, ldw, d); break;
+    case 2: hipLaunchKernelGGL(bupdate_kernel<2>, grid, dim3(NT), sh, s, V, ldv, ncols, H, W, ldw, d); break;
+    case 4: hipLaunchKernelGGL(bupdate_kernel<4>, grid, dim3(NT), sh, s, V, ldv, ncols, H, W, ldw, d); break;
+    case 8: hipLaunchKernelGGL(bupdate_kernel<8>, grid, dim3(NT), sh, s, V, ldv, ncols, H, W, ldw, d); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

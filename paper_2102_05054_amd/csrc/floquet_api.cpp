@@ -610,6 +610,7 @@ fq_status destroy_floquet_op(floquet_op* op) {
   (void)hipFree(op->psi32);
   (void)hipFree(op->out32);
   (void)hipFree(op->coefs_dev);
+  (void)hipFree(op->many_mem);
   (void)hipFree(op->V);
   (void)hipFree(op->work);
   (void)hipFree(op->work2);
@@ -646,6 +647,25 @@ fq_status apply_filter(floquet_op* op, int k, double phi, fq_dtype dtype, const 
     return FQ_EINVAL;
   }
   return filter_internal(op, k, phi, nullptr, dtype, psi_dev, out_dev, static_cast<hipStream_t>(hip_stream));
+}
+
+fq_status apply_filter_many(floquet_op* op, int k, double phi, fq_dtype dtype, int n_vec, const void* psi_dev,
+                            void* out_dev, void* hip_stream) {
+  clear_error();
+  fq_status st = check_ptrs(op, psi_dev, out_dev);
+  if (st != FQ_OK) return st;
+  if (k < 0 || !std::isfinite(phi) || (dtype != FQ_C64 && dtype != FQ_C128) || n_vec < 1 || n_vec > 65535) {
+    set_error("apply_filter_many: need k >= 0, finite phi, a valid dtype and 1 <= n_vec <= 65535");
+    return FQ_EINVAL;
+  }
+  const size_t bytes = op->dim() * size_t(n_vec) * (dtype == FQ_C64 ? sizeof(c64) : sizeof(c128));
+  const char* a = static_cast<const char*>(psi_dev);
+  const char* b = static_cast<const char*>(out_dev);
+  if (a < b + bytes && b < a + bytes) {
+    set_error("apply_filter_many: out must not overlap psi");
+    return FQ_EINVAL;
+  }
+  return filter_many(op, k, phi, dtype, n_vec, psi_dev, out_dev, static_cast<hipStream_t>(hip_stream));
 }
 
 fq_status apply_polynomial(floquet_op* op, int k, const double* coeffs_host, fq_dtype dtype, const void* psi_dev,

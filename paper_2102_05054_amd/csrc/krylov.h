@@ -37,6 +37,11 @@ void warm_start_coefs(unsigned long long seed, int nev, std::vector<c128>* cc);
 fq_status arnoldi_solve(floquet_op* op, int nev, double phi, const fq_arnoldi_opts* o, double* evals_host,
                         void* evecs_dev, double* resid_host, fq_arnoldi_stats* stats, hipStream_t s);
 
+// Block Krylov-Schur solve (arnoldi_eigs with opts->block in {2, 4, 8});
+// the options were validated by the caller.
+fq_status block_solve(floquet_op* op, int nev, double phi, const fq_arnoldi_opts* o, double* evals_host,
+                      void* evecs_dev, double* resid_host, fq_arnoldi_stats* stats, hipStream_t s);
+
 // Lockstep batched solve (arnoldi_eigs_batched); k_per_op may be NULL.
 fq_status arnoldi_batched_solve(floquet_op* const* ops, int n_ops, const double* phis, int n_phi, int nev,
                                 const fq_arnoldi_opts* o, const int* k_per_op, double* evals_host,

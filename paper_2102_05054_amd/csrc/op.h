@@ -81,6 +81,13 @@ struct floquet_op {
   double2* coefs_dev = nullptr;
   size_t coefs_cap = 0;
 
+  // apply_filter_many: device descriptors + problem list of the last call
+  // (re-uploaded only when the vectors, count, precision or tables change)
+  void* many_mem = nullptr;
+  size_t many_cap = 0;
+  const void* many_key[4] = {nullptr, nullptr, nullptr, nullptr};
+  int many_n = 0;
+
   // Krylov workspace (complex128): V (d x ncv_cap+1) and helpers
   void* V = nullptr;
   int ncv_cap = 0;
@@ -108,6 +115,10 @@ fq_status filter_internal(floquet_op* op, int k, double phi, const zd* coefs, fq
 fq_status filter_mixed(floquet_op* op, int k, double phi, const zd* coefs, fq_dtype dt, const void* psi64,
                        void* out64, hipStream_t s);
 fq_status ensure_scratch32(floquet_op* op);
+// out_j = g_k(U) psi_j for n vectors (vector j at offset j*d of psi / out), in dt;
+// kicked Ising: one launch per Horner pass for all n vectors
+fq_status filter_many(floquet_op* op, int k, double phi, fq_dtype dt, int n, const void* psi, void* out,
+                      hipStream_t s);
 // out = a * psi
 fq_status poly_scale_copy(floquet_op* op, zd a, fq_dtype dt, const void* psi, void* out, hipStream_t s);
 

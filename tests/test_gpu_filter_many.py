@@ -1,0 +1,78 @@
+"""GPU parity of apply_filter_many (the filter of a block of vectors, one
+launch per Horner pass for all of them) against the oracle's geometric sum."""
+
+import numpy as np
+import pytest
+
+from gpu_util import bw_op, ki_op, rel, require_gpu, say, to_dev, to_np
+from oracle import filters, models
+from workloads import brickwork, kicked_ising, random_state
+
+pytestmark = pytest.mark.gpu
+
+
+def _dt(name):
+    torch = require_gpu()
+    return torch.complex128 if name == "c128" else torch.complex64
+
+
+def _tol(dt, k):
+    return 1e-12 * (k + 1) if dt == "c128" else 2e-7 * (k + 1) + 2e-6
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("L,n,k,phi", [(4, 3, 7, 0.3), (9, 2, 25, 1.1), (12, 5, 40, 4.0), (16, 4, 12, 0.7),
+                                       (20, 2, 3, 5.0)])
+def test_filter_many_kicked_ising(dt, L, n, k, phi):
+    # single-workgroup shapes (L <= 13) and the multi-pass plan (L = 16, 20)
+    say(f"apply_filter_many L={L} n={n} k={k} {dt}")
+    p = kicked_ising(L, 700 + L)
+    psi = random_state(2 ** L, 31 + L, n)
+    ref = np.stack([filters.geometric_sum(lambda v: models.ki_apply(p, v), psi[j], k, phi) for j in range(n)])
+    with ki_op(p) as op:
+        dpsi = to_dev(psi, _dt(dt))
+        dout = op.apply_filter_many(dpsi, k, phi)
+        out = to_np(dout)
+        # a second call on the same buffers reuses the launch descriptors
+        dpsi.copy_(to_dev(psi[::-1].copy(), _dt(dt)))
+        out2 = to_np(op.apply_filter_many(dpsi, k, phi, out=dout))
+    for j in range(n):
+        assert rel(out[j], ref[j]) < _tol(dt, k), j
+        assert rel(out2[j], ref[n - 1 - j]) < _tol(dt, k), j
+
+
+def test_filter_many_copy_single_vector_and_brickwork():
+    # k = 0 copies; one vector and brickwork ops take the one-by-one path
+    torch = require_gpu()
+    p = kicked_ising(10, 3)
+    psi = random_state(2 ** 10, 4, 3)
+    with ki_op(p) as op:
+        out0 = to_np(op.apply_filter_many(to_dev(psi, torch.complex128), 0, 0.2))
+        one = to_np(op.apply_filter_many(to_dev(psi[:1], torch.complex128), 5, 0.2))
+        ref1 = to_np(op.apply_filter(to_dev(psi[0], torch.complex128), 5, 0.2))
+    assert np.array_equal(out0, psi)
+    assert np.array_equal(one[0], ref1)
+    q = brickwork(8, 11)
+    U = models.dense(q)
+    psi = random_state(2 ** 8, 6, 2)
+    with bw_op(q) as op:
+        out = to_np(op.apply_filter_many(to_dev(psi, torch.complex128), 9, 1.7))
+    for j in range(2):
+        assert rel(out[j], filters.geometric_sum(lambda v: U @ v, psi[j], 9, 1.7)) < 1e-11
+
+
+def test_filter_many_argument_errors():
+    torch = require_gpu()
+    from paper_2102_05054_amd import FloquetError
+    from paper_2102_05054_amd._lib import FQ_C128, lib
+    p = kicked_ising(6, 1)
+    with ki_op(p) as op:
+        psi = to_dev(random_state(64, 1, 2), torch.complex128)
+        with pytest.raises(FloquetError):
+            op.apply_filter_many(psi, -1, 0.0)
+        with pytest.raises(FloquetError):
+            op.apply_filter_many(psi, 3, float("nan"))
+        # overlapping buffers (out shifted by one vector into psi)
+        buf = torch.zeros((3, 64), dtype=torch.complex128, device="cuda")
+        st = lib().apply_filter_many(op.handle, 3, 0.0, FQ_C128, 2, buf.data_ptr(), buf[1].data_ptr(), None)
+        assert st != 0
