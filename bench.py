@@ -16,8 +16,13 @@ batched call), --workload bw_L24 (the brickwork filter at L = 24),
 --scan-L L (an (ncv, k) runtime scan), --profile-filter (for counter runs).
 
 One step = one complete arnoldi_eigs solve (filter, CGS2, restart, Ritz
-vectors, FP64 residuals, refinement) in complex64 + FP64 refinement.
+vectors, FP64 residuals, refinement) in complex64 + FP64 refinement, block
+Krylov-Schur with 4 vectors per filter launch (--block); the complex128
+comparison solve uses 2 (--block-c128), the faster setting of each path.
 value = U-applications per second over the timed steps (whole job).
+roofline = the pass kernel that takes most of the timed solve (the FP64
+refinement's complex128 pass, or the complex64 pass), timed with HIP events
+in the launch configuration the solve uses (block vectors per launch).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--k K] [--no-c128] [--no-cpu]
 """
@@ -48,7 +53,10 @@ def parse():
     ap.add_argument("--W", type=float, default=1.0)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--max-restarts", type=int, default=60)
-    ap.add_argument("--block", type=int, default=1, help="vectors filtered per Krylov step (1, 2, 4, 8)")
+    ap.add_argument("--block", type=int, default=4,
+                    help="vectors filtered per Krylov step of the complex64 + FP64 solve (1, 2, 4, 8)")
+    ap.add_argument("--block-c128", type=int, default=2,
+                    help="vectors filtered per Krylov step of the complex128 comparison solve")
     ap.add_argument("--no-c128", action="store_true", help="skip the complex128 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--roofline-steps", type=int, default=2000)
@@ -58,51 +66,72 @@ def parse():
                     help="ki_batched: 256 realisations x 4 targets, L in 12..16, one batched call; "
                          "bw_L24: the brickwork filter (k=300) at L=24")
     ap.add_argument("--profile-filter", action="store_true",
-                    help="only the complex64 Horner filter (k=200) and a 64 MiB device copy, for counter runs")
+                    help="only the Horner filters (k=200, complex64 then complex128, --block vectors per launch) "
+                         "and the calibration copies, for counter runs")
     return ap.parse_args()
 
 
-def filter_roofline(op, L, steps):
-    """Average duration of the Horner pass kernel (complex64) from HIP events
-    on the launch stream; algorithmic bytes per pass = 3 * 8 * 2^L."""
+def filter_roofline(op, L, steps, nvec=1, dtype="c64"):
+    """Average duration of the Horner pass kernel from HIP events on the
+    launch stream, with nvec vectors per launch (apply_filter_many) as in a
+    block solve; algorithmic bytes per pass = nvec * 3 * (8 or 16) * 2^L
+    (read w and psi, write w)."""
     import torch
     d = 2 ** L
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    esize = 8 if dtype == "c64" else 16
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
-        psi = torch.randn(d, dtype=torch.complex64, device="cuda")
+        psi = torch.randn((nvec, d), dtype=tdt, device="cuda")
         out = torch.empty_like(psi)
-        op.apply_filter(psi, 50, 0.0, out=out, stream=s)  # warm (tables, plans)
+
+        def run(kk):
+            if nvec == 1:
+                op.apply_filter(psi[0], kk, 0.0, out=out[0], stream=s)
+            else:
+                op.apply_filter_many(psi, kk, 0.0, out=out, stream=s)
+
+        run(steps)  # warm: tables, plans and the tile tuner for this k
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(s)
-        op.apply_filter(psi, steps, 0.0, out=out, stream=s)
+        run(steps)
         e1.record(s)
     s.synchronize()
     ms = e0.elapsed_time(e1)
     launches = steps + 1  # k Horner passes + the prologue kick pass
     avg_s = ms * 1e-3 / launches
-    bytes_per_launch = 3 * 8 * d
+    bytes_per_launch = nvec * 3 * esize * d
+    real = "float" if dtype == "c64" else "double"
     return {
-        "kernel": "ki_pass_kernel<float,...> (Horner step: kick, phase, +psi, kick)",
+        "kernel": f"ki_pass_kernel<{real},...> ({nvec} vector(s) per launch; Horner step: kick, phase, +psi, kick)",
+        "dtype": dtype,
+        "vectors_per_launch": nvec,
         "avg_launch_us": avg_s * 1e6,
         "bytes_per_launch": bytes_per_launch,
         "achieved_GBs": bytes_per_launch / avg_s / 1e9,
-        "U_apps_per_s": 1.0 / avg_s,
+        "U_apps_per_s": nvec / avg_s,
     }
 
 
 COPY_BYTES = 2 ** 30
 
 
-def profile_filter(op, L):
-    """Workload of the counter runs: 200 Horner passes (complex64) and one plain
-    device-to-device copy of COPY_BYTES (1 GiB, source evicted from L2 and the
-    Infinity Cache by a second 1 GiB write) that calibrates FETCH_SIZE /
-    WRITE_SIZE in bytes."""
+def profile_filter(op, L, nvec):
+    """Workload of the counter runs: 200 Horner passes in complex64, then 200
+    in complex128, nvec vectors per launch, and two plain device copies of
+    COPY_BYTES (1 GiB, source evicted from L2 and the Infinity Cache by a
+    second 1 GiB write) that calibrate FETCH_SIZE / WRITE_SIZE in bytes."""
     import torch
-    psi = torch.randn(2 ** L, dtype=torch.complex64, device="cuda")
-    out = torch.empty_like(psi)
-    op.apply_filter(psi, 200, 0.0, out=out)
+    for tdt in (torch.complex64, torch.complex128):
+        psi = torch.randn((nvec, 2 ** L), dtype=tdt, device="cuda")
+        out = torch.empty_like(psi)
+        if nvec == 1:
+            op.apply_filter(psi[0], 200, 0.0, out=out[0])
+        else:
+            op.apply_filter_many(psi, 200, 0.0, out=out)
+        torch.cuda.synchronize()
+        del psi, out
     a = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda").fill_(1)
     c = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda").fill_(2)
     b = torch.empty_like(a)
@@ -111,18 +140,23 @@ def profile_filter(op, L):
     torch.mul(c.view(torch.float32), 1.0, out=a.view(torch.float32))
     torch.cuda.synchronize()
     del c
-    print(json.dumps({"profile_filter": True, "L": L, "copy_bytes": COPY_BYTES}))
+    print(json.dumps({"profile_filter": True, "L": L, "vectors_per_launch": nvec, "copy_bytes": COPY_BYTES}))
 
 
-def traffic_per_pass():
-    """Calibrated HBM bytes per pass from the committed counter summary, only
-    when it was measured on the current kernel source."""
+def traffic_file(nvec):
+    name = "ki_pass_kernel_L20_traffic.json" if nvec == 1 else f"ki_pass_kernel_L20_block{nvec}_traffic.json"
+    return os.path.join(ROOT, "profiles", name)
+
+
+def traffic_per_pass(nvec, dtype):
+    """Calibrated HBM bytes per pass launch (nvec vectors) from the committed
+    counter summary, only when it was measured on the current kernel source."""
     try:
         from paper_2102_05054_amd.traffic import kernel_hash
-        with open(os.path.join(ROOT, "profiles", "ki_pass_kernel_L20_traffic.json")) as f:
+        with open(traffic_file(nvec)) as f:
             rec = json.load(f)
         if rec.get("kernel_hash") == kernel_hash():
-            return rec["bytes_per_pass"]
+            return rec.get(f"bytes_per_pass_{dtype}", rec["bytes_per_pass"] if dtype == "c64" else None)
     except (OSError, ValueError, KeyError):
         pass
     return None
@@ -385,28 +419,29 @@ def main():
     d = 2 ** L
 
     if args.profile_filter:
-        profile_filter(op, L)
+        profile_filter(op, L, args.block)
         op.close()
         return
 
-    def solve(dtype):
+    def solve(dtype, block):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ev, _, res, st, status = op.arnoldi_eigs(args.nev, 0.0, k=k, ncv=args.ncv, tol=args.tol,
                                                  max_restarts=args.max_restarts, filter_dtype=dtype,
                                                  refine=True, seed=1, want_vectors=False,
-                                                 allow_not_converged=True, block=args.block)
+                                                 allow_not_converged=True, block=block)
         torch.cuda.synchronize()
         return time.perf_counter() - t0, ev, res, st, status
 
     for _ in range(args.warmup):
-        solve("c64")
+        solve("c64", args.block)
     torch.cuda.synchronize()
     t_total = 0.0
     uapps = 0
     runs = []
     for _ in range(args.steps):
-        dt, ev, res, st, status = solve("c64")
+        dt, ev, res, st, status = solve("c64", args.block)
+        print(f"[bench] c64+refine solve: {dt:.1f} s, status {int(status)}", file=sys.stderr, flush=True)
         t_total += dt
         uapps += st["n_U_apps"]
         runs.append((dt, res, st, status))
@@ -414,11 +449,19 @@ def main():
 
     c128 = None
     if not args.no_c128:
-        dt2, ev2, res2, st2, status2 = solve("c128")
+        dt2, ev2, res2, st2, status2 = solve("c128", args.block_c128)
+        print(f"[bench] c128 solve: {dt2:.1f} s, status {int(status2)}", file=sys.stderr, flush=True)
         c128 = {"time_s": dt2, "status": int(status2), "nconv": st2["nconv"], "max_residual": float(res2.max()),
-                "n_U_apps": st2["n_U_apps"], "n_restarts": st2["n_restarts"], "t_filter_s": st2["t_filter"]}
+                "n_U_apps": st2["n_U_apps"], "n_restarts": st2["n_restarts"], "t_filter_s": st2["t_filter"],
+                "block": args.block_c128}
 
-    roof = filter_roofline(op, L, args.roofline_steps)
+    # the refinement's complex128 passes or the complex64 passes: whichever
+    # phase took longer in the timed solve bounds it
+    t_ref = last_st["t_refine"]
+    dom = "c128" if t_ref > 0.5 * last_dt else "c64"
+    roof = filter_roofline(op, L, args.roofline_steps, args.block, dom)
+    other = filter_roofline(op, L, args.roofline_steps, args.block, "c64" if dom == "c128" else "c128")
+    print(f"[bench] roofline: {roof['avg_launch_us']:.2f} us per {dom} pass", file=sys.stderr, flush=True)
     cpu = None if args.no_cpu else cpu_baseline(p)
 
     value = uapps / t_total
@@ -437,7 +480,8 @@ def main():
         "data": "synthetic (seeded kicked-Ising couplings)",
         "config": {
             "workload": f"kicked Ising L={L} (d={d}), W={args.W}, nev={args.nev}, ncv={args.ncv}, "
-                        f"k={k} (paper rule 0.8*2^(L+1)/ncv), phi=0, tol={args.tol}, block={args.block}",
+                        f"k={k} (paper rule 0.8*2^(L+1)/ncv), phi=0, tol={args.tol}, "
+                        f"block Krylov-Schur with {args.block} vectors per filter launch",
             "L": L, "nev": args.nev, "ncv": args.ncv, "k": k, "phi": 0.0, "block": args.block,
         },
         "time_to_eigenpairs_s": {"c64+refine": last_dt, "c128": c128["time_s"] if c128 else None},
@@ -455,11 +499,20 @@ def main():
             "peak": 8000.0,
             "unit": "GB/s",
             "frac": roof["achieved_GBs"] / 8000.0,
-            "traffic": traffic_per_pass(),
+            "traffic": traffic_per_pass(args.block, dom),
             "kernel": roof["kernel"],
             "avg_launch_us": roof["avg_launch_us"],
             "bytes_per_launch": roof["bytes_per_launch"],
             "filter_U_apps_per_s": roof["U_apps_per_s"],
+            "share_of_solve": (t_ref if dom == "c128" else last_dt - t_ref) / last_dt,
+        },
+        "roofline_other_pass": {
+            "kernel": other["kernel"],
+            "achieved": other["achieved_GBs"],
+            "frac": other["achieved_GBs"] / 8000.0,
+            "avg_launch_us": other["avg_launch_us"],
+            "bytes_per_launch": other["bytes_per_launch"],
+            "traffic": traffic_per_pass(args.block, other["dtype"]),
         },
         "cpu_baseline": cpu,
     }

@@ -3,9 +3,10 @@
 rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) over ``bench.py --profile-filter``
 reports KiB per dispatch for the pass kernels and for a plain device copy of
 known size (the calibration: the copy moves exactly ``copy_bytes`` each way).
-``summarise`` turns the two counter CSVs into bytes per pass launch, scaled by
-the copy's known / measured ratio, and records the hash of the kernel source so
-that a stale measurement is never reported for a changed kernel.
+``summarise`` turns the two counter CSVs into bytes per pass launch (complex64
+and complex128 passes separately), scaled by the copy's known / measured
+ratio, and records the hash of the kernel source so that a stale measurement
+is never reported for a changed kernel.
 
 Usage:
   python -m paper_2102_05054_amd.traffic FETCH.csv WRITE.csv COPY_BYTES OUT.json
@@ -61,15 +62,21 @@ def summarise(fetch_csv, write_csv, copy_bytes):
     w_factor = copy_bytes / (write[cname] * 1024.0)
     passes = {}
     for k in fetch:
-        if "ki_pass_kernel<float" in k:
+        if "ki_pass_kernel<float" in k or "ki_pass_kernel<double" in k:
             passes[k] = {
                 "fetch_bytes": fetch[k] * 1024.0 * f_factor,
                 "write_bytes": write.get(k, 0.0) * 1024.0 * w_factor,
                 "dispatches": nf[k],
             }
-    tot_f = sum(v["fetch_bytes"] * v["dispatches"] for v in passes.values())
-    tot_w = sum(v["write_bytes"] * v["dispatches"] for v in passes.values())
-    n = sum(v["dispatches"] for v in passes.values())
+
+    def per_pass(tag):
+        sel = [v for k, v in passes.items() if tag in k]
+        n = sum(v["dispatches"] for v in sel)
+        if n == 0:
+            return None
+        return sum((v["fetch_bytes"] + v["write_bytes"]) * v["dispatches"] for v in sel) / n
+
+    c64 = per_pass("ki_pass_kernel<float")
     return {
         "kernel_hash": kernel_hash(),
         "copy_kernel": cname,
@@ -78,7 +85,9 @@ def summarise(fetch_csv, write_csv, copy_bytes):
         "fetch_factor": f_factor,
         "write_factor": w_factor,
         "per_kernel": passes,
-        "bytes_per_pass": (tot_f + tot_w) / max(n, 1),
+        "bytes_per_pass": c64,
+        "bytes_per_pass_c64": c64,
+        "bytes_per_pass_c128": per_pass("ki_pass_kernel<double"),
     }
 
 
