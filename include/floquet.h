@@ -244,6 +244,21 @@ fq_status entanglement_entropy(const floquet_op* op, int LA, const void* states_
  */
 fq_status fq_paper_parameters(int L, int nev, int* ncv_out, int* k_out);
 
+/*
+ * Kernel choice of the batched kicked-Ising passes (arnoldi_eigs_batched,
+ * apply_filter_many, block solves), process-wide:
+ *   FQ_POLICY_AUTO (0): the autotuner times one-workgroup-per-tile and
+ *     persistent pipelined passes and keeps the faster (default);
+ *   FQ_POLICY_TILE (1): one workgroup per tile only;
+ *   FQ_POLICY_PIPE (2): persistent pipelined passes wherever a tile shape has
+ *     them (a workgroup loads its next tile while it works on the current one).
+ * All three compute the same arithmetic.  Changing the policy drops the
+ * tuner's cached choices.  FQ_EINVAL for other values.  Not thread-safe with
+ * concurrent solves.
+ */
+enum { FQ_POLICY_AUTO = 0, FQ_POLICY_TILE = 1, FQ_POLICY_PIPE = 2 };
+fq_status fq_set_kernel_policy(int policy);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* floquet_last_error(void);
 

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libfloquet.so")
 
 FQ_OK, FQ_NOT_CONVERGED, FQ_EINVAL, FQ_ENOMEM, FQ_EDEVICE, FQ_ENUMERIC = 0, 1, -1, -2, -3, -4
 FQ_C64, FQ_C128 = 0, 1
+FQ_POLICY_AUTO, FQ_POLICY_TILE, FQ_POLICY_PIPE = 0, 1, 2
 FQ_KICKED_ISING, FQ_BRICKWORK, FQ_CIRCUIT = 0, 1, 2
 
 STATUS_NAMES = {
@@ -67,6 +68,7 @@ SIGNATURES = [
                                      POINTER(FqArnoldiOpts), POINTER(c_int), POINTER(c_double),
                                      POINTER(c_void_p), POINTER(c_double), POINTER(FqArnoldiStats), c_void_p]),
     ("floquet_last_error", ctypes.c_char_p, []),
+    ("fq_set_kernel_policy", c_int, [c_int]),
     ("fq_host_schur", c_int, [c_int, POINTER(c_double), POINTER(c_double), POINTER(c_double)]),
     ("fq_paper_parameters", c_int, [c_int, c_int, POINTER(c_int), POINTER(c_int)]),
     ("fq_host_eigvalsh", c_int, [c_int, POINTER(c_double), POINTER(c_double)]),

@@ -540,6 +540,11 @@ fq_status filter_many_ki(floquet_op* op, int k, double phi, int n, const void* p
 
 }  // namespace
 
+extern "C" fq_status fq_set_kernel_policy(int policy) {
+  clear_error();
+  return ki_set_policy(policy);
+}
+
 fq_status filter_many(floquet_op* op, int k, double phi, fq_dtype dt, int n, const void* psi, void* out,
                       hipStream_t s) {
   if (op->model == FQ_KICKED_ISING && op->L >= 4 && k >= 1 && n > 1)

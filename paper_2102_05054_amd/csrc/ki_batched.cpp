@@ -23,6 +23,15 @@ bool shape_compiled(int rb, int tb) {
   return false;
 }
 
+// (RB, TB) pairs with a pipelined instance (ki_launch_pipe)
+bool pipe_shape(int rb, int tb, bool c64_dt) {
+  static const int S[][2] = {{2, 8}, {3, 7}, {3, 8}, {3, 9}, {4, 6}, {4, 7}, {4, 8}, {4, 9}};
+  if (!c64_dt && rb > 3) return false;
+  for (const auto& x : S)
+    if (x[0] == rb && x[1] == tb) return true;
+  return false;
+}
+
 bool group_ok(const KiGroup& g, size_t d) {
   return g.n >= g.tb && g.rb >= 0 && g.rb + g.tb == g.n && g.rb <= 4 && g.tb <= 9 && g.tb <= g.rb + 6 &&
          (size_t(g.ntiles) << g.n) == d && shape_compiled(g.rb, g.tb);
@@ -59,7 +68,8 @@ fq_status bpass(const KiBatchShape& sh, const KiGroup& g, const KiDesc<Real>* de
   a.psi_coef_re = 1.0;
   a.in_coef_re = 1.0;
   // few tiles in the whole launch: latency-bound, fetch the phase with the tile
-  if (size_t(g.ntiles) * n <= (sizeof(Real) == 4 ? 1024u : 512u)) a.flags |= KI_PREFETCH_PHASE;
+  if (sh.prefetch > 0 || (sh.prefetch < 0 && size_t(g.ntiles) * n <= (sizeof(Real) == 4 ? 1024u : 512u)))
+    a.flags |= KI_PREFETCH_PHASE;
   a.k1 = masks_for(g.kbits, g.n, g.rb, g.tb);
   a.k2 = k2 ? a.k1 : KickMasks{0, 0, 0, 0};
   a.desc = desc;
@@ -68,6 +78,15 @@ fq_status bpass(const KiBatchShape& sh, const KiGroup& g, const KiDesc<Real>* de
   a.flat = sh.flat ? 1 : 0;
   a.tile_log = 0;
   while ((1u << a.tile_log) < g.ntiles) ++a.tile_log;
+  if (sh.pipe > 0 && pipe_shape(g.rb, g.tb, sizeof(Real) == 4)) {
+    const size_t items = size_t(g.ntiles) * n;
+    const unsigned grid = static_cast<unsigned>(std::min<size_t>(sh.pipe, (items / 2) & ~size_t(7)));
+    if (grid >= 8 && (g.ntiles & 7u) == 0u) {
+      const hipError_t e = ki_launch_pipe<Real>(a, g.rb, g.tb, sh.sw, g.ntiles, n, grid, s);
+      if (e != hipSuccess) return launch_err("pipelined kicked-Ising pass launch failed", e);
+      return FQ_OK;
+    }
+  }
   const hipError_t e = ki_launch_pass<Real>(a, g.rb, g.tb, sh.sw, g.ntiles, s, n);
   if (e != hipSuccess) return launch_err("batched kicked-Ising pass launch failed", e);
   return FQ_OK;
@@ -210,6 +229,7 @@ fq_status ki_batch_apply(const KiBatchShape& sh, const KiDesc<Real>* desc, const
 namespace {
 std::mutex g_tune_mu;
 std::map<std::tuple<int, bool, bool, int, int>, KiBatchShape> g_tuned;
+int g_policy = FQ_POLICY_AUTO;  // guarded by g_tune_mu
 
 // FQ_VERBOSE=1 prints the tuner's choice to stderr.
 bool tune_verbose() {
@@ -227,13 +247,26 @@ int size_class(unsigned n) {
 }
 }  // namespace
 
+fq_status ki_set_policy(int policy) {
+  if (policy != FQ_POLICY_AUTO && policy != FQ_POLICY_TILE && policy != FQ_POLICY_PIPE) {
+    set_error("fq_set_kernel_policy: policy must be FQ_POLICY_AUTO, FQ_POLICY_TILE or FQ_POLICY_PIPE");
+    return FQ_EINVAL;
+  }
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  if (policy != g_policy) g_tuned.clear();
+  g_policy = policy;
+  return FQ_OK;
+}
+
 template <typename Real>
 fq_status ki_batch_tune(int L, bool sw, int k, const KiDesc<Real>* desc, const int* list, unsigned n,
                         hipStream_t s, KiBatchShape* out, double* best_us) {
   const bool c64_dt = sizeof(Real) == 4;
   const auto key = std::make_tuple(L, sw, c64_dt, k, size_class(n));
+  int policy;
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
+    policy = g_policy;
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) {
       *out = it->second;
@@ -291,6 +324,24 @@ fq_status ki_batch_tune(int L, bool sw, int k, const KiDesc<Real>* desc, const i
     KiBatchShape c = best;
     c.flat = true;
     consider(c);
+    for (int pf : {0, 1}) {
+      KiBatchShape q = best;
+      q.prefetch = pf;
+      consider(q);
+    }
+    // stage 4: persistent pipelined passes, 1, 2 or 4 workgroups per CU
+    // (the only choice under FQ_POLICY_PIPE, skipped under FQ_POLICY_TILE)
+    int dev = 0, cus = 0;
+    if (policy != FQ_POLICY_TILE && hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) {
+      const KiBatchShape base2 = best;
+      if (policy == FQ_POLICY_PIPE) best_t = -1.0;
+      for (unsigned per_cu : {1u, 2u, 4u}) {
+        KiBatchShape p = base2;
+        p.pipe = (static_cast<unsigned>(cus) * per_cu) & ~7u;
+        if (p.pipe >= 8) consider(p);
+      }
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -299,14 +350,14 @@ fq_status ki_batch_tune(int L, bool sw, int k, const KiDesc<Real>* desc, const i
     return FQ_EDEVICE;
   }
   if (tune_verbose())
-    std::fprintf(stderr, "[fq] tuned L=%d %s n=%u k=%d: %s rb/tb %d/%d chunk %u flat %d: %.2f us/step\n", L,
-                 c64_dt ? "c64" : "c128", n, k, best.single ? "single" : "multi-pass",
+    std::fprintf(stderr, "[fq] tuned L=%d %s n=%u k=%d: %s rb/tb %d/%d chunk %u flat %d prefetch %d pipe %u: %.2f us/step\n",
+                 L, c64_dt ? "c64" : "c128", n, k, best.single ? "single" : "multi-pass",
                  best.single ? best.srb : best.plan.grp[0].rb, best.single ? best.stb : best.plan.grp[0].tb,
-                 best.chunk, best.flat ? 1 : 0, best_t);
+                 best.chunk, best.flat ? 1 : 0, best.prefetch, best.pipe, best_t);
   *out = best;
   if (best_us) *best_us = best_t;
   std::lock_guard<std::mutex> g(g_tune_mu);
-  g_tuned[key] = best;
+  if (g_policy == policy) g_tuned[key] = best;
   return FQ_OK;
 }
 

@@ -23,6 +23,13 @@ struct KiBatchShape {
   // Infinity Cache across passes; `flat` keeps each problem on one XCD
   unsigned chunk = 0;
   bool flat = false;
+  // multi-pass only: persistent pipelined passes with this many workgroups
+  // (0 = one workgroup per tile); a group with fewer than two tiles per
+  // workgroup, or without a pipelined instance, keeps one workgroup per tile
+  unsigned pipe = 0;
+  // phase-table entries fetched with the tile (1), mid-pass (0), or by the
+  // tile-count rule (-1): fetching early costs registers and occupancy
+  int prefetch = -1;
 };
 
 // Candidate shapes for (L, kick form, precision), the default first.
@@ -39,9 +46,13 @@ template <typename Real>
 fq_status ki_batch_apply(const KiBatchShape& sh, const KiDesc<Real>* desc, const int* list, unsigned n,
                          hipStream_t s);
 
-// Autotuner: times the candidate shapes on the given problems (their psi and
-// x buffers are overwritten) for min(k, 32) Horner steps, then the sub-batch
-// sizes and the XCD mapping for the fastest shape, and returns the fastest
+// fq_set_kernel_policy: which pass forms the autotuner may pick.
+fq_status ki_set_policy(int policy);
+
+// Autotuner: times the candidate shapes on the given problems (their x
+// buffers are overwritten) for min(k, 32) Horner steps, then the sub-batch
+// sizes, the XCD mapping, the phase-table prefetch and the pipelined
+// persistent form (1, 2, 4 workgroups per CU) for the fastest shape, and returns the fastest
 // combination; results are cached per (L, kick form, precision, k, batch size
 // class).  best_us (optional) receives the time per Horner step of the batch.
 template <typename Real>

@@ -80,6 +80,14 @@ struct KiSingleArgs {
 template <typename Real>
 hipError_t ki_launch_pass(const KiPassArgs<Real>& a, int rb, int tb, bool sw, unsigned ntiles, hipStream_t s,
                           unsigned nprob = 0);
+// Persistent pipelined form of a batched pass: `grid` workgroups (a multiple
+// of 8, at most nprob * ntiles) walk the (problem, tile) items, each loading
+// its next tile while it works on the current one.  a.tile_log = log2 ntiles;
+// a.flat is ignored.  Shapes: (RB, TB) in {(2,8), (3,7), (3,8), (3,9)}, and
+// (4,6..9) in complex64.
+template <typename Real>
+hipError_t ki_launch_pipe(const KiPassArgs<Real>& a, int rb, int tb, bool sw, unsigned ntiles, unsigned nprob,
+                          unsigned grid, hipStream_t s);
 template <typename Real>
 hipError_t ki_launch_single(const KiSingleArgs<Real>& a, int rb, int tb, bool sw, bool psi_regs,
                             unsigned nblocks, hipStream_t s, bool batched = false);

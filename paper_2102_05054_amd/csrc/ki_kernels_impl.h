@@ -114,7 +114,7 @@ __device__ __forceinline__ cpx<Real> ki_phase(const cpx<Real>* __restrict__ tlo,
                                               const cpx<Real>* __restrict__ thi, uint32_t g, int m) {
   const uint32_t lo = g & ((1u << m) - 1u);
   const uint32_t hi = ((g >> m) << 2) | ((g & 1u) << 1) | ((g >> (m - 1)) & 1u);
-  return cmul(tlo[lo], thi[hi]);
+  return cmul(gload(tlo, lo), gload(thi, hi));
 }
 
 // ---------------------------------------------------------------------------
@@ -169,10 +169,10 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
   // so every global access of the pass is coalesced.
   C v[R], ps[R], tl[PF ? R : 1], th[PF ? R : 1];
 #pragma unroll
-  for (int m = 0; m < R; ++m) v[m] = xin[tm.g(tid + (m << TB))];
+  for (int m = 0; m < R; ++m) v[m] = gload(xin, tm.g(tid + (m << TB)));
   if (do_ps) {
 #pragma unroll
-    for (int m = 0; m < R; ++m) ps[m] = psi[tm.g(tid + (m << TB))];
+    for (int m = 0; m < R; ++m) ps[m] = gload(psi, tm.g(tid + (m << TB)));
   }
   // with few tiles per CU (small states) the pass is latency-bound: fetch the
   // phase-table entries together with the tile instead of mid-pass
@@ -181,8 +181,8 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
 #pragma unroll
     for (int m = 0; m < R; ++m) {
       const uint32_t g = tm.g(tid + (m << TB));
-      tl[m] = tlo[g & ((1u << a.m) - 1u)];
-      th[m] = thi[((g >> a.m) << 2) | ((g & 1u) << 1) | ((g >> (a.m - 1)) & 1u)];
+      tl[m] = gload(tlo, g & ((1u << a.m) - 1u));
+      th[m] = gload(thi, ((g >> a.m) << 2) | ((g & 1u) << 1) | ((g >> (a.m - 1)) & 1u));
     }
   }
   if (a.flags & KI_SCALE_IN) {
@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
     a_to_b<Real, RB, TB>(v, lds, tid);
     kick_regs<Real, RB, SW>(v, a.k1.regB, w);
     kick_lanes<Real, RB, SW>(v, a.k1.laneB, w);
-    if constexpr (RB > 0) __syncthreads();
+    if constexpr (RB > 0) lds_barrier();
     b_to_a<Real, RB, TB>(v, lds, tid);
   }
 
@@ -222,16 +222,157 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
   kick_regs<Real, RB, SW>(v, a.k2.regA, w);
   kick_lanes<Real, RB, SW>(v, a.k2.laneA, w);
   if (a.k2.regB | a.k2.laneB) {
-    if constexpr (RB > 0) __syncthreads();
+    if constexpr (RB > 0) lds_barrier();
     a_to_b<Real, RB, TB>(v, lds, tid);
     kick_regs<Real, RB, SW>(v, a.k2.regB, w);
     kick_lanes<Real, RB, SW>(v, a.k2.laneB, w);
-    if constexpr (RB > 0) __syncthreads();
+    if constexpr (RB > 0) lds_barrier();
     b_to_a<Real, RB, TB>(v, lds, tid);
   }
 
 #pragma unroll
-  for (int m = 0; m < R; ++m) xout[tm.g(tid + (m << TB))] = v[m];
+  for (int m = 0; m < R; ++m) gstore(xout, tm.g(tid + (m << TB)), v[m]);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent, software-pipelined form of a batched pass.  The grid (a
+// multiple of 8 workgroups) walks the nitems = nprob * 2^tile_log (problem,
+// tile) items, problem-major; workgroup g runs on XCD g mod 8 and takes
+// every (grid/8)-th item of that XCD's contiguous eighth of the items, so
+// neighbouring tiles share one L2.  Per item the loads of psi and of the
+// phase-table entries of the current tile are issued first and the next
+// tile's state after them: the in-order memory counter then lets the next
+// tile's loads stay in flight through the kicks, the phase and the store of
+// the current one.  Arithmetic and layout changes are those of
+// ki_pass_kernel.
+// ---------------------------------------------------------------------------
+template <typename Real>
+struct KiPipeItem {
+  const cpx<Real>* xin;
+  cpx<Real>* xout;
+  const cpx<Real>* psi;
+  const cpx<Real>* tlo;
+  const cpx<Real>* thi;
+  Real w;
+  TileMap tm;
+};
+
+// desc / list arrive as restrict kernel parameters: read-only for the
+// kernel, so the compiler loads them through the scalar cache (lgkmcnt), not
+// with vector loads that would have to wait behind the prefetch (vmcnt).
+template <typename Real>
+__device__ __forceinline__ KiPipeItem<Real> ki_pipe_item(const KiPassArgs<Real>& a, const KiDesc<Real>* __restrict__ desc,
+                                                         const int* __restrict__ list, uint32_t item) {
+  const uint32_t q = item >> a.tile_log;
+  const uint32_t tile = item & ((1u << a.tile_log) - 1u);
+  const KiDesc<Real>& D = desc[list[q]];
+  KiPipeItem<Real> r;
+  r.xin = a.from_psi ? D.psi : D.x;
+  r.xout = D.x;
+  r.psi = D.psi;
+  r.tlo = D.tlo;
+  r.thi = D.thi;
+  r.w = static_cast<Real>(D.w);
+  r.tm = make_tile_map(tile, a.n, a.c, a.p);
+  return r;
+}
+
+// s_waitcnt immediate that waits until at most n vector memory operations
+// are outstanding (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt and
+// lgkmcnt left at their maxima)
+template <int N>
+constexpr int vmcnt_imm() {
+  static_assert(N >= 0 && N < 64, "vmcnt is six bits");
+  return 0x0F70 | (N & 15) | ((N >> 4) << 14);
+}
+
+template <typename Real, int RB, int TB, bool SW>
+__global__ void __launch_bounds__(1 << TB)
+    ki_pipe_kernel(KiPassArgs<Real> a, uint32_t nitems, const KiDesc<Real>* __restrict__ desc,
+                   const int* __restrict__ list) {
+  using C = cpx<Real>;
+  constexpr int R = 1 << RB;
+  extern __shared__ char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int tid = threadIdx.x;
+  const uint32_t per_xcd = nitems >> 3;
+  const uint32_t stride = gridDim.x >> 3;
+  const uint32_t first = (blockIdx.x & 7u) * per_xcd;
+  uint32_t local = blockIdx.x >> 3;
+  if (local >= per_xcd) return;
+  const bool do_ph = (a.flags & KI_PHASE) != 0;
+  const bool do_ps = (a.flags & KI_ADD_PSI) != 0;
+  const uint32_t mlo = (1u << a.m) - 1u;
+
+  KiPipeItem<Real> cur = ki_pipe_item(a, desc, list, first + local);
+  C v[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) v[m] = gload(cur.xin, cur.tm.g(tid + (m << TB)));
+  for (;;) {
+    // this tile's state (the previous iteration's prefetch) has arrived once
+    // at most the R stores issued after it are outstanding
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm<R>());
+    // this tile's psi and phase entries, then the next tile's state.  The
+    // loads are issued whatever the flags and also for the last item (which
+    // re-reads its own tile): with one load sequence on every path the
+    // compiler's wait counts stay exact and never drain the prefetch.
+    C ps[R], tl[R], th[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) ps[m] = gload(cur.psi, cur.tm.g(tid + (m << TB)));
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const uint32_t g = cur.tm.g(tid + (m << TB));
+      tl[m] = gload(cur.tlo, g & mlo);
+      th[m] = gload(cur.thi, ((g >> a.m) << 2) | ((g & 1u) << 1) | ((g >> (a.m - 1)) & 1u));
+    }
+    const uint32_t here = first + local;
+    local += stride;
+    const bool more = local < per_xcd;
+    const KiPipeItem<Real> nxt = ki_pipe_item(a, desc, list, more ? first + local : here);
+    C vn[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) vn[m] = gload(nxt.xin, nxt.tm.g(tid + (m << TB)));
+    // keep the prefetch ahead of the work below (no sinking towards its use)
+    asm volatile("" ::: "memory");
+
+    const Real w = cur.w;
+    kick_regs<Real, RB, SW>(v, a.k1.regA, w);
+    kick_lanes<Real, RB, SW>(v, a.k1.laneA, w);
+    if (a.k1.regB | a.k1.laneB) {
+      a_to_b<Real, RB, TB>(v, lds, tid);
+      kick_regs<Real, RB, SW>(v, a.k1.regB, w);
+      kick_lanes<Real, RB, SW>(v, a.k1.laneB, w);
+      if constexpr (RB > 0) lds_barrier();
+      b_to_a<Real, RB, TB>(v, lds, tid);
+    }
+    if (do_ph || do_ps) {
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        C x = v[m];
+        if (do_ph) x = cmul(x, cmul(tl[m], th[m]));
+        if (do_ps) x = cadd(x, ps[m]);
+        v[m] = x;
+      }
+    }
+    kick_regs<Real, RB, SW>(v, a.k2.regA, w);
+    kick_lanes<Real, RB, SW>(v, a.k2.laneA, w);
+    if (a.k2.regB | a.k2.laneB) {
+      if constexpr (RB > 0) lds_barrier();
+      a_to_b<Real, RB, TB>(v, lds, tid);
+      kick_regs<Real, RB, SW>(v, a.k2.regB, w);
+      kick_lanes<Real, RB, SW>(v, a.k2.laneB, w);
+      if constexpr (RB > 0) lds_barrier();
+      b_to_a<Real, RB, TB>(v, lds, tid);
+    }
+#pragma unroll
+    for (int m = 0; m < R; ++m) gstore(cur.xout, cur.tm.g(tid + (m << TB)), v[m]);
+    if (!more) break;
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = vn[m];
+    cur = nxt;
+    // the next tile's layout changes reuse the LDS read above
+    if constexpr (RB > 0) lds_barrier();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -360,6 +501,21 @@ hipError_t launch_pass_t(const KiPassArgs<Real>& a, unsigned ntiles, unsigned np
   return hipGetLastError();
 }
 
+template <typename Real, int RB, int TB, bool SW>
+hipError_t launch_pipe_t(const KiPassArgs<Real>& a, uint32_t nitems, unsigned grid, hipStream_t s) {
+  const size_t shmem = static_cast<size_t>(lds_slots<RB, TB>()) * sizeof(cpx<Real>);
+  auto kern = ki_pipe_kernel<Real, RB, TB, SW>;
+  static bool attr_set = false;
+  if (!attr_set && shmem > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(1 << TB), shmem, s, a, nitems, a.desc, a.list);
+  return hipGetLastError();
+}
+
 template <typename Real, int RB, int TB, bool SW, bool PSI_REGS, bool BATCH>
 hipError_t launch_single_tt(const KiSingleArgs<Real>& a, unsigned nblocks, hipStream_t s) {
   const size_t shmem = static_cast<size_t>(lds_slots<RB, TB>()) * sizeof(cpx<Real>);
@@ -412,6 +568,35 @@ hipError_t ki_launch_pass(const KiPassArgs<Real>& a, int rb, int tb, bool sw, un
   FQ_SHAPES(FQ_CASE)
 #undef FQ_CASE
 #undef FQ_CASE4
+  return hipErrorInvalidValue;
+}
+
+// complex128 with 16 amplitudes per thread would spill (prefetched state,
+// psi and two phase factors live at once): no pipelined instance
+template <typename Real, int RB, int TB>
+hipError_t launch_pipe_sw(const KiPassArgs<Real>& a, bool sw, uint32_t nitems, unsigned grid, hipStream_t s) {
+  if constexpr (sizeof(Real) == 8 && RB > 3) {
+    return hipErrorInvalidValue;
+  } else {
+    return sw ? launch_pipe_t<Real, RB, TB, true>(a, nitems, grid, s)
+              : launch_pipe_t<Real, RB, TB, false>(a, nitems, grid, s);
+  }
+}
+
+// multi-pass tile shapes with a pipelined instance
+#define FQ_PIPE_SHAPES(X) X(2, 8) X(3, 7) X(3, 8) X(3, 9) X(4, 6) X(4, 7) X(4, 8) X(4, 9)
+
+template <typename Real>
+hipError_t ki_launch_pipe(const KiPassArgs<Real>& a, int rb, int tb, bool sw, unsigned ntiles, unsigned nprob,
+                          unsigned grid, hipStream_t s) {
+  if (!a.desc || !a.list || nprob == 0 || nprob > 65535u || ntiles != (1u << a.tile_log) || (ntiles & 7u) != 0u)
+    return hipErrorInvalidValue;
+  const size_t nitems = size_t(ntiles) * nprob;
+  if (nitems > 0x7fffffffu || grid == 0 || (grid & 7u) != 0u || grid > nitems) return hipErrorInvalidValue;
+#define FQ_CASE(RB_, TB_) \
+  if (rb == RB_ && tb == TB_) return launch_pipe_sw<Real, RB_, TB_>(a, sw, static_cast<uint32_t>(nitems), grid, s);
+  FQ_PIPE_SHAPES(FQ_CASE)
+#undef FQ_CASE
   return hipErrorInvalidValue;
 }
 

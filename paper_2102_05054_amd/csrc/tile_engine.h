@@ -65,13 +65,55 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t bid, uint32_t ntiles) {
   return (bid & 7u) * (ntiles >> 3) + (bid >> 3);
 }
 
+// Global-memory accesses of amplitudes through address-space-1 pointers.
+// Pointers read from a descriptor are generic, and the compiler would emit
+// flat accesses, which also count in the LDS/scalar counter (lgkmcnt): every
+// LDS wait would then drain the state loads in flight as well.
+template <typename Real>
+struct gvec2;
+template <>
+struct gvec2<float> {
+  typedef float __attribute__((ext_vector_type(2))) type;
+};
+template <>
+struct gvec2<double> {
+  typedef double __attribute__((ext_vector_type(2))) type;
+};
+
+template <typename Real>
+__device__ __forceinline__ cpx<Real> gload(const cpx<Real>* p, uint32_t i) {
+  using V = typename gvec2<Real>::type;
+  typedef const __attribute__((address_space(1))) V* GP;
+  const V v = ((GP)p)[i];  // C-style: reinterpret and address-space cast
+  return mk<Real>(v.x, v.y);
+}
+
+template <typename Real>
+__device__ __forceinline__ void gstore(cpx<Real>* p, uint32_t i, cpx<Real> c) {
+  using V = typename gvec2<Real>::type;
+  V v;
+  v.x = c.x;
+  v.y = c.y;
+  typedef __attribute__((address_space(1))) V* GP;
+  ((GP)p)[i] = v;
+}
+
+// Workgroup barrier that orders LDS accesses only: global loads still in
+// flight (a prefetch, psi) are not waited for, unlike __syncthreads(), whose
+// release fence drains every outstanding memory access.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Layout A <-> B through LDS.  The caller synchronises before reuse.
 template <typename Real, int RB, int TB>
 __device__ __forceinline__ void a_to_b(cpx<Real> (&v)[1 << RB], cpx<Real>* lds, int tid) {
   if constexpr (RB > 0) {
 #pragma unroll
     for (int m = 0; m < (1 << RB); ++m) lds[lds_phys<RB>(tid + (m << TB))] = v[m];
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int m = 0; m < (1 << RB); ++m) v[m] = lds[lds_phys<RB>((tid << RB) + m)];
   }
@@ -82,7 +124,7 @@ __device__ __forceinline__ void b_to_a(cpx<Real> (&v)[1 << RB], cpx<Real>* lds, 
   if constexpr (RB > 0) {
 #pragma unroll
     for (int m = 0; m < (1 << RB); ++m) lds[lds_phys<RB>((tid << RB) + m)] = v[m];
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int m = 0; m < (1 << RB); ++m) v[m] = lds[lds_phys<RB>(tid + (m << TB))];
   }

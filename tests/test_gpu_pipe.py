@@ -1,0 +1,79 @@
+"""GPU parity of the persistent pipelined kicked-Ising passes
+(FQ_POLICY_PIPE) against the oracle, next to the one-workgroup-per-tile
+passes (FQ_POLICY_TILE) on the same inputs."""
+
+import numpy as np
+import pytest
+
+from gpu_util import ki_op, rel, require_gpu, say, to_dev, to_np
+from oracle import filters, models
+from workloads import CONFIGS, config_kicked_ising, kicked_ising, random_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture
+def policy():
+    from paper_2102_05054_amd._lib import FQ_POLICY_AUTO, check, lib
+
+    def set_policy(p):
+        check(lib().fq_set_kernel_policy(int(p)), "fq_set_kernel_policy")
+
+    yield set_policy
+    set_policy(FQ_POLICY_AUTO)
+
+
+def _tol(dt, k):
+    return 1e-12 * (k + 1) if dt == "c128" else 2e-7 * (k + 1) + 2e-6
+
+
+# tile groups per (L, precision): L = 16 complex64 has one pipelined group
+# (2^10 tiles) and one without a pipelined shape (2^9); L = 18 and 20 have
+# pipelined shapes for both groups in both precisions
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("L,n,k,phi", [(16, 5, 9, 0.4), (18, 3, 6, 2.2), (20, 2, 3, 5.0)])
+def test_pipelined_filter_matches_oracle(policy, dt, L, n, k, phi):
+    from paper_2102_05054_amd._lib import FQ_POLICY_PIPE, FQ_POLICY_TILE
+    torch = require_gpu()
+    tdt = torch.complex128 if dt == "c128" else torch.complex64
+    say(f"pipelined filter L={L} n={n} k={k} {dt}")
+    p = kicked_ising(L, 800 + L)
+    psi = random_state(2 ** L, 51 + L, n)
+    ref = np.stack([filters.geometric_sum(lambda v: models.ki_apply(p, v), psi[j], k, phi) for j in range(n)])
+    outs = {}
+    with ki_op(p) as op:
+        for pol in (FQ_POLICY_PIPE, FQ_POLICY_TILE):
+            policy(pol)
+            outs[pol] = to_np(op.apply_filter_many(to_dev(psi, tdt), k, phi))
+    for j in range(n):
+        assert rel(outs[FQ_POLICY_PIPE][j], ref[j]) < _tol(dt, k), j
+        assert rel(outs[FQ_POLICY_TILE][j], ref[j]) < _tol(dt, k), j
+        # the two forms may pick different tile shapes (another butterfly order)
+        assert rel(outs[FQ_POLICY_PIPE][j], outs[FQ_POLICY_TILE][j]) < _tol(dt, k), j
+
+
+def test_pipelined_block_solve_L16(policy):
+    # full-size kicked Ising L = 16 workload through the block solver with
+    # the pipelined complex64 passes; eigenvalues as the single-vector solve
+    from paper_2102_05054_amd._lib import FQ_POLICY_PIPE
+    c = CONFIGS["ki_L16"]
+    p = config_kicked_ising("ki_L16")
+    with ki_op(p) as op:
+        ev1, _, res1, _, _ = op.arnoldi_eigs(c["nev"], p.phi, k=c["k"], ncv=c["ncv"], tol=1e-10, seed=2,
+                                             want_vectors=False)
+        policy(FQ_POLICY_PIPE)
+        ev4, vecs, res4, st4, _ = op.arnoldi_eigs(c["nev"], p.phi, k=c["k"], ncv=c["ncv"], tol=1e-10,
+                                                  filter_dtype="c64", seed=2, block=4)
+        vecs = to_np(vecs)
+    say(st4)
+    assert res4.max() <= 1e-10
+    assert np.max(np.abs(np.sort_complex(ev1) - np.sort_complex(ev4))) < 1e-12
+    for n in (0, c["nev"] - 1):
+        assert np.linalg.norm(models.ki_apply(p, vecs[n]) - ev4[n] * vecs[n]) < 1e-10
+
+
+def test_policy_argument_errors():
+    from paper_2102_05054_amd._lib import lib
+    assert lib().fq_set_kernel_policy(3) != 0
+    assert lib().fq_set_kernel_policy(-1) != 0
+    assert lib().fq_set_kernel_policy(0) == 0
