@@ -191,14 +191,15 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
     for (int m = 0; m < R; ++m) v[m] = cmul(v[m], s);
   }
 
-  // first kick of this group: layout A, then layout B, back to A
+  // first kick of this group: layout A, then layout B, back to A.  A thread
+  // rewrites only LDS slots it read itself (B slots in b_to_a, A slots in
+  // the next a_to_b), so the barrier inside each layout change suffices.
   kick_regs<Real, RB, SW>(v, a.k1.regA, w);
   kick_lanes<Real, RB, SW>(v, a.k1.laneA, w);
   if (a.k1.regB | a.k1.laneB) {
     a_to_b<Real, RB, TB>(v, lds, tid);
     kick_regs<Real, RB, SW>(v, a.k1.regB, w);
     kick_lanes<Real, RB, SW>(v, a.k1.laneB, w);
-    if constexpr (RB > 0) lds_barrier();
     b_to_a<Real, RB, TB>(v, lds, tid);
   }
 
@@ -222,11 +223,9 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
   kick_regs<Real, RB, SW>(v, a.k2.regA, w);
   kick_lanes<Real, RB, SW>(v, a.k2.laneA, w);
   if (a.k2.regB | a.k2.laneB) {
-    if constexpr (RB > 0) lds_barrier();
     a_to_b<Real, RB, TB>(v, lds, tid);
     kick_regs<Real, RB, SW>(v, a.k2.regB, w);
     kick_lanes<Real, RB, SW>(v, a.k2.laneB, w);
-    if constexpr (RB > 0) lds_barrier();
     b_to_a<Real, RB, TB>(v, lds, tid);
   }
 
@@ -338,11 +337,10 @@ __global__ void __launch_bounds__(1 << TB)
     const Real w = cur.w;
     kick_regs<Real, RB, SW>(v, a.k1.regA, w);
     kick_lanes<Real, RB, SW>(v, a.k1.laneA, w);
-    if (a.k1.regB | a.k1.laneB) {
+    if (a.k1.regB | a.k1.laneB) {  // as in ki_pass_kernel: no barrier between layout changes
       a_to_b<Real, RB, TB>(v, lds, tid);
       kick_regs<Real, RB, SW>(v, a.k1.regB, w);
       kick_lanes<Real, RB, SW>(v, a.k1.laneB, w);
-      if constexpr (RB > 0) lds_barrier();
       b_to_a<Real, RB, TB>(v, lds, tid);
     }
     if (do_ph || do_ps) {
@@ -357,11 +355,9 @@ __global__ void __launch_bounds__(1 << TB)
     kick_regs<Real, RB, SW>(v, a.k2.regA, w);
     kick_lanes<Real, RB, SW>(v, a.k2.laneA, w);
     if (a.k2.regB | a.k2.laneB) {
-      if constexpr (RB > 0) lds_barrier();
       a_to_b<Real, RB, TB>(v, lds, tid);
       kick_regs<Real, RB, SW>(v, a.k2.regB, w);
       kick_lanes<Real, RB, SW>(v, a.k2.laneB, w);
-      if constexpr (RB > 0) lds_barrier();
       b_to_a<Real, RB, TB>(v, lds, tid);
     }
 #pragma unroll
@@ -370,8 +366,8 @@ __global__ void __launch_bounds__(1 << TB)
 #pragma unroll
     for (int m = 0; m < R; ++m) v[m] = vn[m];
     cur = nxt;
-    // the next tile's layout changes reuse the LDS read above
-    if constexpr (RB > 0) lds_barrier();
+    // the next tile's layout changes write only LDS slots this thread read
+    // last (its layout-A slots): no barrier needed here either
   }
 }
 
