@@ -104,3 +104,44 @@ def test_block_argument_errors():
             kw.update(bad)
             with pytest.raises(FloquetError):
                 op.arnoldi_eigs(6, 0.0, **kw)
+
+
+def test_block_start_vectors_follow_the_counter_generator():
+    # the library's seeded start vector equals the counter generator's
+    # (implemented independently in workloads): passing it as v0 gives the
+    # bitwise same solve
+    torch = require_gpu()
+    from workloads import counter_uniform_complex
+    p = kicked_ising(9, 21)
+    v0 = counter_uniform_complex(2 ** 9, 5)
+    with ki_op(p) as op:
+        a = op.arnoldi_eigs(6, 0.8, k=30, ncv=24, tol=1e-10, seed=5, want_vectors=False, block=2)
+        b = op.arnoldi_eigs(6, 0.8, k=30, ncv=24, tol=1e-10, seed=5, want_vectors=False, block=2,
+                            v0=to_dev(v0, torch.complex128))
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
+
+
+def test_block_dependent_and_ill_conditioned_start_blocks():
+    # column c >= 1 of the start block is the seeded vector of seed + c; a v0
+    # equal to column 1 makes the block rank deficient (clear error), one
+    # 1e-8 away from it takes the Gram-Schmidt fallback of the block
+    # orthonormalisation (Cholesky QR would lose the second direction) and
+    # still converges to the zgeev pairs
+    torch = require_gpu()
+    from paper_2102_05054_amd import FloquetError
+    from workloads import counter_uniform_complex
+    p = kicked_ising(9, 22)
+    d = 2 ** 9
+    U = models.ki_dense(p)
+    om_ref, _ = eig.full_closest(U, 6, 2.5)
+    v1 = counter_uniform_complex(d, 7 + 1)
+    with ki_op(p) as op:
+        with pytest.raises(FloquetError, match="rank deficient"):
+            op.arnoldi_eigs(6, 2.5, k=30, ncv=24, tol=1e-10, seed=7, want_vectors=False, block=2,
+                            v0=to_dev(v1, torch.complex128))
+        near = v1 + 1e-8 * counter_uniform_complex(d, 90)
+        ev, _, res, st, status = op.arnoldi_eigs(6, 2.5, k=30, ncv=24, tol=1e-10, seed=7, want_vectors=False,
+                                                 block=2, v0=to_dev(near, torch.complex128))
+    assert status == 0
+    assert np.max(np.abs(ev - om_ref)) < 1e-12
+    assert res.max() <= 1e-10

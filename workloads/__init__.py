@@ -38,6 +38,7 @@ __all__ = [
     "circuit_from_brickwork",
     "kicked_ising",
     "brickwork",
+    "counter_uniform_complex",
     "brickwork_layout",
     "brickwork_cz",
     "haar_unitary",
@@ -209,6 +210,39 @@ def start_vector(d: int, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed + 1)
     v = rng.standard_normal(d) + 1j * rng.standard_normal(d)
     return (v / np.linalg.norm(v)).astype(np.complex128)
+
+
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_MIX1 = np.uint64(0xBF58476D1CE4E5B9)
+_MIX2 = np.uint64(0x94D049BB133111EB)
+_SEED_MUL = np.uint64(0x100000001B3)
+
+
+def _splitmix64(x: np.ndarray) -> np.ndarray:
+    """SplitMix64 finaliser (Steele, Lea and Flood 2014; constants as in
+    Vigna's public reference implementation), elementwise on uint64."""
+    x = x + _GOLDEN
+    x = (x ^ (x >> np.uint64(30))) * _MIX1
+    x = (x ^ (x >> np.uint64(27))) * _MIX2
+    return x ^ (x >> np.uint64(31))
+
+
+def counter_uniform_complex(d: int, seed: int) -> np.ndarray:
+    """Counter-based start vector: entry i = (2u - 1) + i(2u' - 1) with u, u'
+    the top 53 bits of SplitMix64(seed * 0x100000001B3 + 2i) and of
+    SplitMix64(seed * 0x100000001B3 + 2i + 1), scaled to [0, 1).  The library
+    draws its seeded start vectors from the same published generator (its own
+    implementation), so a test can build start blocks with known relations to
+    them.  Not normalised."""
+    with np.errstate(over="ignore"):
+        base = np.uint64(seed) * _SEED_MUL
+        i = np.arange(d, dtype=np.uint64)
+        a = _splitmix64(base + np.uint64(2) * i)
+        b = _splitmix64(base + np.uint64(2) * i + np.uint64(1))
+    scale = 1.0 / 9007199254740992.0
+    ua = (a >> np.uint64(11)).astype(np.float64) * scale
+    ub = (b >> np.uint64(11)).astype(np.float64) * scale
+    return (2.0 * ua - 1.0) + 1j * (2.0 * ub - 1.0)
 
 
 def random_state(d: int, seed: int, count: int = 1) -> np.ndarray:
