@@ -65,6 +65,9 @@ def parse():
     ap.add_argument("--workload", default="ki_L20", choices=["ki_L20", "ki_batched", "bw_L24"],
                     help="ki_batched: 256 realisations x 4 targets, L in 12..16, one batched call; "
                          "bw_L24: the brickwork filter (k=300) at L=24")
+    ap.add_argument("--profile-gemm", action="store_true",
+                    help="only solves with filter order 1 (two restarts each), for counter runs of the FP64 "
+                         "matrix-core basis rotation")
     ap.add_argument("--profile-filter", action="store_true",
                     help="only the Horner filters (k=200, complex64 then complex128, --block vectors per launch) "
                          "and the calibration copies, for counter runs")
@@ -141,6 +144,23 @@ def profile_filter(op, L, nvec):
     torch.cuda.synchronize()
     del c
     print(json.dumps({"profile_filter": True, "L": L, "vectors_per_launch": nvec, "copy_bytes": COPY_BYTES}))
+
+
+def profile_gemm(op, L, ncv, nev, block):
+    """Workload of the matrix-core counter runs: complex128 Krylov-Schur at
+    filter order 1 for two restarts (block 1 and the given block), so that the
+    restart rotation V_m Z_p (d x m by m x p, complex FP64) and the Ritz products
+    dominate the few other kernels.  Prints the rotation's algorithmic flops."""
+    import torch
+    for b in sorted({1, block}):
+        op.arnoldi_eigs(nev, 0.0, k=1, ncv=ncv, tol=1e-10, max_restarts=2, filter_dtype="c128", seed=1,
+                        want_vectors=False, allow_not_converged=True, block=b)
+    torch.cuda.synchronize()
+    d = 2 ** L
+    m = ncv
+    p = min(m - 1, max(nev + 1, nev + (m - nev) // 2))
+    print(json.dumps({"profile_gemm": True, "L": L, "m": m, "p": p,
+                      "rotation_flop": 8 * d * m * p, "rotation_bytes": 16 * d * (m + p)}))
 
 
 def traffic_file(nvec):
@@ -418,6 +438,10 @@ def main():
     op = kicked_ising(p.L, p.J, p.h, p.g, p.periodic)
     d = 2 ** L
 
+    if args.profile_gemm:
+        profile_gemm(op, L, args.ncv, args.nev, args.block)
+        op.close()
+        return
     if args.profile_filter:
         profile_filter(op, L, args.block)
         op.close()
