@@ -387,6 +387,72 @@ __global__ void __launch_bounds__(64) basis_gemm_mfma_kernel(const c128* __restr
   basis_gemm_mfma_body(V, ldv, m, Q, p, Y, ldy, blockIdx.x);
 }
 
+// Same product with 64 rows per workgroup (4 waves of 16 rows): chunks of
+// kGemmKc rows of Q are staged through LDS, so that a workgroup reads Q once
+// from L2 for 64 rows of V instead of once per 16, and four waves share each
+// chunk.  Y may equal V: a workgroup writes only its own rows, after all of
+// its reads.
+// MAXT: 16-column tiles of Y a wave accumulates (>= ceil(p / 16)); fewer
+// tiles, fewer accumulator registers, more waves per SIMD.
+constexpr int kGemmKc = 8;
+template <int MAXT>
+__global__ void __launch_bounds__(256) basis_gemm_mfma64_kernel(const c128* __restrict__ V, size_t ldv, int m,
+                                                                const c128* __restrict__ Q, int p, c128* Y,
+                                                                size_t ldy) {
+  extern __shared__ char gemm_smem[];
+  c128* qs = reinterpret_cast<c128*>(gemm_smem);  // kGemmKc x p
+  const int tid = threadIdx.x;
+  const int l = tid & 63;
+  const size_t r0 = static_cast<size_t>(blockIdx.x) * 64 + 16 * (tid >> 6);
+  const int ntile = (p + 15) >> 4;
+  fq_d4 accr[MAXT], acci[MAXT];
+#pragma unroll
+  for (int t = 0; t < MAXT; ++t) {
+    accr[t] = fq_d4{0.0, 0.0, 0.0, 0.0};
+    acci[t] = fq_d4{0.0, 0.0, 0.0, 0.0};
+  }
+  const int lr = l & 15, lk = l >> 4;
+  for (int c0 = 0; c0 < m; c0 += kGemmKc) {
+    const int kc = min(kGemmKc, m - c0);
+    __syncthreads();  // the previous chunk has been read
+    for (int e = tid; e < kGemmKc * p; e += 256) {
+      const int kk = e / p;
+      qs[e] = kk < kc ? Q[size_t(c0 + kk) * p + (e - kk * p)] : mk<double>(0, 0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k0 = 0; k0 < kGemmKc; k0 += 4) {
+      const int kk = k0 + lk;
+      const c128 a = kk < kc ? V[size_t(c0 + kk) * ldv + r0 + lr] : mk<double>(0, 0);
+      const double nai = -a.y;
+#pragma unroll
+      for (int t = 0; t < MAXT; ++t) {
+        if (t < ntile) {
+          const int col = (t << 4) + lr;
+          const c128 b = col < p ? qs[kk * p + col] : mk<double>(0, 0);
+          accr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, accr[t], 0, 0, 0);
+          accr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, b.y, accr[t], 0, 0, 0);
+          acci[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, acci[t], 0, 0, 0);
+          acci[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, acci[t], 0, 0, 0);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < MAXT; ++t) {
+    if (t < ntile) {
+      const int col = (t << 4) + lr;
+      if (col < p) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 4 * r + lk;
+          Y[size_t(col) * ldy + r0 + i] = mk<double>(accr[t][r], acci[t][r]);
+        }
+      }
+    }
+  }
+}
+
 // Gram matrix G[i][j] = sum_t A(i,t) conj(A(j,t)), A(i,t) = X[i*si + t*st]
 // (conjugated if cj): 16x16 output tiles, 64-long t chunks staged in LDS.
 __global__ void __launch_bounds__(256) gram_kernel(const c128* __restrict__ X, size_t si, size_t st, int cj, int n,
@@ -819,6 +885,20 @@ hipError_t launch_axpy_dev(const c128* a, const c128* x, c128* y, size_t d, hipS
 
 hipError_t launch_basis_gemm(const c128* V, size_t ldv, int m, const c128* Q, int p, c128* Y, size_t ldy, size_t d,
                              hipStream_t s) {
+  if (p <= 256 && d % 64 == 0 && d >= 64) {
+    const size_t shmem = size_t(kGemmKc) * p * sizeof(c128);  // <= 32 KB
+    const dim3 grid(static_cast<unsigned>(d / 64));
+    const int ntile = (p + 15) / 16;
+    if (ntile <= 4)
+      hipLaunchKernelGGL(basis_gemm_mfma64_kernel<4>, grid, dim3(256), shmem, s, V, ldv, m, Q, p, Y, ldy);
+    else if (ntile <= 8)
+      hipLaunchKernelGGL(basis_gemm_mfma64_kernel<8>, grid, dim3(256), shmem, s, V, ldv, m, Q, p, Y, ldy);
+    else if (ntile <= 12)
+      hipLaunchKernelGGL(basis_gemm_mfma64_kernel<12>, grid, dim3(256), shmem, s, V, ldv, m, Q, p, Y, ldy);
+    else
+      hipLaunchKernelGGL(basis_gemm_mfma64_kernel<16>, grid, dim3(256), shmem, s, V, ldv, m, Q, p, Y, ldy);
+    return hipGetLastError();
+  }
   if (p <= 256 && d % 16 == 0 && d >= 16) {
     hipLaunchKernelGGL(basis_gemm_mfma_kernel, dim3(static_cast<unsigned>(d / 16)), dim3(64), 0, s, V, ldv, m, Q, p,
                        Y, ldy);

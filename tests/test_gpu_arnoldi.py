@@ -117,3 +117,21 @@ def test_user_polynomial_filter_batched():
     finally:
         for o in ops:
             o.close()
+
+
+def test_wide_restart_rotation_against_dense():
+    # n_ev = 150, n_cv = 300 at L = 11: the restart keeps p = 225 Schur vectors
+    # and the Ritz product has 150 columns, so the FP64 matrix-core rotation
+    # runs with 15 and 10 column tiles of 16 (the L = 20 bench: 160 and 100);
+    # k = 15 keeps the 150 closest eigenvalues inside the filter's main lobe
+    say("arnoldi wide rotation L=11 nev=150 ncv=300")
+    p = kicked_ising(11, 314)
+    U = models.ki_dense(p)
+    om_ref, _ = eig.full_closest(U, 150, 1.0)
+    with ki_op(p) as op:
+        ev, _, res, st, status = op.arnoldi_eigs(150, 1.0, k=15, ncv=300, tol=1e-10, seed=2, want_vectors=False,
+                                                 max_restarts=400)
+    say(st)
+    assert status == 0
+    assert np.max(np.abs(ev - om_ref)) < 1e-12
+    assert res.max() <= 1e-10
