@@ -415,7 +415,7 @@ def cpu_baseline(p, seconds=15.0):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1 (multi-GPU sharding is a design note only)"}))
         sys.exit(2)
     import numpy as np
     import torch
