@@ -76,3 +76,19 @@ def test_filter_many_argument_errors():
         buf = torch.zeros((3, 64), dtype=torch.complex128, device="cuda")
         st = lib().apply_filter_many(op.handle, 3, 0.0, FQ_C128, 2, buf.data_ptr(), buf[1].data_ptr(), None)
         assert st != 0
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("L,n,k", [(10, 64, 5), (14, 16, 3), (18, 3, 1)])
+def test_filter_many_many_vectors_and_order_one(dt, L, n, k):
+    # many vectors per launch (the single-workgroup form at L = 10, the
+    # multi-pass one at L = 14) and k = 1 (the prologue pass and one Horner
+    # pass only)
+    say(f"apply_filter_many L={L} n={n} k={k} {dt}")
+    p = kicked_ising(L, 730 + L)
+    psi = random_state(2 ** L, 60 + L, n)
+    with ki_op(p) as op:
+        out = to_np(op.apply_filter_many(to_dev(psi, _dt(dt)), k, 2.9))
+    for j in (0, n // 2, n - 1):
+        ref = filters.geometric_sum(lambda v: models.ki_apply(p, v), psi[j], k, 2.9)
+        assert rel(out[j], ref) < _tol(dt, k), j
