@@ -396,7 +396,8 @@ PAPER_BW_SECONDS = {10: 0.3, 11: 0.7, 12: 2.3, 13: 6.6, 14: 26.0, 15: 46.8, 16: 
 def brickwork_paper(args):
     """The paper's own benchmark problem: the 50 eigenpairs closest to z = 1
     of a brickwork Haar circuit of L sites, complex128 (the paper's precision),
-    tol 1e-10.  n_cv = min(floor(2^(L/2+1)), 256) and k by the paper's rule
+    tol 1e-10, block Krylov-Schur with --block-c128 vectors per filter launch.
+    n_cv = min(floor(2^(L/2+1)), 256) and k by the paper's rule
     0.8 * 2^(L+1) / n_cv for that n_cv: the (n_cv, k) scans at L = 12, 14 find
     smaller n_cv faster than the paper's, and n_cv in the thousands would make
     the host Schur step of each restart the bottleneck.  The paper's time for
@@ -414,7 +415,8 @@ def brickwork_paper(args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev, _, res, st, status = op.arnoldi_eigs(nev, 0.0, k=k, ncv=ncv, tol=1e-10, max_restarts=args.max_restarts,
-                                             filter_dtype="c128", seed=1, want_vectors=False, allow_not_converged=True)
+                                             filter_dtype="c128", seed=1, want_vectors=False, allow_not_converged=True,
+                                             block=args.block_c128)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     op.close()
@@ -425,7 +427,8 @@ def brickwork_paper(args):
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "c128",
         "data": "synthetic (seeded Haar-random two-site gates)",
         "config": {"workload": f"brickwork Haar circuit L={L} (d={2 ** L}), nev=50, z=1, ncv={ncv}, k={k} "
-                               f"(0.8*2^(L+1)/ncv), tol=1e-10, complex128", "L": L, "ncv": ncv, "k": k},
+                               f"(0.8*2^(L+1)/ncv), tol=1e-10, complex128", "L": L, "ncv": ncv, "k": k,
+                   "block": args.block_c128},
         "solve": {"status": int(status), "nconv": st["nconv"], "max_residual": float(res.max()),
                   "n_restarts": st["n_restarts"], "n_U_apps": st["n_U_apps"], "t_filter_s": st["t_filter"],
                   "t_restart_s": st["t_restart"]},

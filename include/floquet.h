@@ -121,10 +121,11 @@ fq_status apply_filter(floquet_op* op, int k, double phi, fq_dtype dtype,
  * out_j = g_k(U) psi_j for n_vec vectors at once (Sec. 3, Eq. (geo); the
  * filter of a block of Krylov vectors, Sec. 4).  psi_dev / out_dev hold n_vec
  * states of dtype back to back (vector j at offset j*d); out must not overlap
- * psi.  Kicked-Ising ops (L >= 4, k >= 1) advance all vectors in one launch
- * per Horner pass (tile shape picked by a timing autotuner on the first call
- * for each (k, precision, vector-count class), which also writes out); other
- * ops filter the vectors one after another.  Calls on one op must not run
+ * psi.  Every op advances all vectors in one launch per Horner pass:
+ * kicked-Ising ops (L >= 4, k >= 1) with a tile shape picked by a timing
+ * autotuner on the first call for each (k, precision, vector-count class),
+ * which also writes out; brickwork and circuit ops with their two tile passes
+ * over (vector, tile) work items.  Calls on one op must not run
  * concurrently on different streams (the op's launch descriptors are shared).
  * Asynchronous on hip_stream.  FQ_EINVAL for k < 0, non-finite phi, n_vec
  * outside 1..65535 or overlapping buffers.

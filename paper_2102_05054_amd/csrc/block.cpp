@@ -167,7 +167,7 @@ struct BlockSolver {
     void* hp = nullptr;
     FQ_HIP_CHECK(hipHostMalloc(&hp, size_t(m + b) * b * 2 * sizeof(c128), hipHostMallocDefault));
     host = static_cast<c128*>(hp);
-    batched_filter = op->model == FQ_KICKED_ISING && coefs.empty() && op->L >= 4;
+    batched_filter = coefs.empty() && (op->model != FQ_KICKED_ISING || op->L >= 4);
     if (batched_filter) {
       FQ_TRY(alloc(&psi32, d * size_t(b)));
       FQ_TRY(alloc(&x32, d * size_t(b)));
@@ -550,6 +550,7 @@ fq_status filter_many(floquet_op* op, int k, double phi, fq_dtype dt, int n, con
   if (op->model == FQ_KICKED_ISING && op->L >= 4 && k >= 1 && n > 1)
     return dt == FQ_C64 ? filter_many_ki<float>(op, k, phi, n, psi, out, s)
                         : filter_many_ki<double>(op, k, phi, n, psi, out, s);
+  if (op->model != FQ_KICKED_ISING && k >= 1 && n > 1) return bw_filter(op, k, phi, nullptr, dt, psi, out, s, n);
   const size_t bytes = op->dim() * (dt == FQ_C64 ? sizeof(c64) : sizeof(c128));
   for (int j = 0; j < n; ++j)
     FQ_TRY(filter_internal(op, k, phi, nullptr, dt, static_cast<const char*>(psi) + size_t(j) * bytes,

@@ -28,6 +28,9 @@ struct BwWin {
 };
 static_assert(sizeof(BwWin) == 8, "BwWin is read as one 64-bit word");
 
+// A launch covers nvec vectors of vstride amplitudes each (vector v at
+// offset v * vstride of xin, xout and psi); its work items are (vector, tile)
+// pairs, item = v * 2^tile_bits + tile.
 struct BwPassArgs {
   const void* xin;
   void* xout;
@@ -38,10 +41,13 @@ struct BwPassArgs {
   int nwin;
   int n, c, p;
   int flags;
+  int tile_bits;  // log2(tiles per vector)
+  unsigned long long vstride;
   double rot_re, rot_im;
   double psi_coef_re, psi_coef_im;
 };
 
-hipError_t bw_launch_pass(const BwPassArgs& a, bool c64_dt, int wb, unsigned ntiles, hipStream_t s);
+// nitems = tiles per vector x vectors
+hipError_t bw_launch_pass(const BwPassArgs& a, bool c64_dt, int wb, unsigned nitems, hipStream_t s);
 
 }  // namespace fq

@@ -153,10 +153,11 @@ __global__ void __launch_bounds__(1 << TB)
   C* lds = reinterpret_cast<C*>(smem_raw);
   const int tid = threadIdx.x;
   const int N = 1 << a.n;
-  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-  const TileMap tm = make_tile_map(tile, a.n, a.c, a.p);
-  const C* __restrict__ xin = static_cast<const C*>(a.xin);
-  C* __restrict__ xout = static_cast<C*>(a.xout);
+  const uint32_t item = xcd_tile(blockIdx.x, gridDim.x);
+  const TileMap tm = make_tile_map(item & ((1u << a.tile_bits) - 1u), a.n, a.c, a.p);
+  const size_t voff = size_t(item >> a.tile_bits) * a.vstride;
+  const C* __restrict__ xin = static_cast<const C*>(a.xin) + voff;
+  C* __restrict__ xout = static_cast<C*>(a.xout) + voff;
   for (int j = tid; j < N; j += T) lds[bw_phys(j)] = xin[tm.g(j)];
   __syncthreads();
   const int ngroups = N >> WB;
@@ -179,7 +180,7 @@ __global__ void __launch_bounds__(1 << TB)
   }
   const C rot = mk<Real>(static_cast<Real>(a.rot_re), static_cast<Real>(a.rot_im));
   const C pc = mk<Real>(static_cast<Real>(a.psi_coef_re), static_cast<Real>(a.psi_coef_im));
-  const C* __restrict__ psi = static_cast<const C*>(a.psi);
+  const C* __restrict__ psi = static_cast<const C*>(a.psi) + voff;
   for (int j = tid; j < N; j += T) {
     const uint32_t g = tm.g(j);
     C x = lds[bw_phys(j)];
@@ -190,13 +191,13 @@ __global__ void __launch_bounds__(1 << TB)
 }
 
 // Persistent, software-pipelined form for tiles of 2^NB amplitudes
-// (2^(NB - WB - TB) window groups per thread): each workgroup walks its tiles
-// (XCD-aware order), and while the windows of one tile run in LDS the next
-// tile is already on its way into registers.  Tiles are disjoint, so
-// in-place passes (xin == xout) stay correct.
+// (2^(NB - WB - TB) window groups per thread): each workgroup walks its
+// (vector, tile) items (XCD-aware order), and while the windows of one tile
+// run in LDS the next tile is already on its way into registers.  Tiles are
+// disjoint, so in-place passes (xin == xout) stay correct.
 template <typename Real, int WB, int TB, int NB, bool PSI>
 __global__ void __launch_bounds__(1 << TB)
-    bw_pipe_kernel(BwPassArgs a, unsigned ntiles, const cpx<Real>* __restrict__ mats, const BwWin* __restrict__ wins,
+    bw_pipe_kernel(BwPassArgs a, unsigned nitems, const cpx<Real>* __restrict__ mats, const BwWin* __restrict__ wins,
                    const BwGate* __restrict__ gates, cpx<Real>* __restrict__ xout) {
   using C = cpx<Real>;
   constexpr int T = 1 << TB, N = 1 << NB, NPT = N / T;
@@ -210,22 +211,28 @@ __global__ void __launch_bounds__(1 << TB)
   const C* psi = static_cast<const C*>(a.psi);
   const C rot = mk<Real>(static_cast<Real>(a.rot_re), static_cast<Real>(a.rot_im));
   const C pc = mk<Real>(static_cast<Real>(a.psi_coef_re), static_cast<Real>(a.psi_coef_im));
+  const uint32_t tmask = (1u << a.tile_bits) - 1u;
   unsigned bid = blockIdx.x;
-  if (bid >= ntiles) return;
-  TileMap tm = make_tile_map(xcd_tile(bid, ntiles), NB, a.c, a.p);
+  if (bid >= nitems) return;
+  const uint32_t item = xcd_tile(bid, nitems);
+  TileMap tm = make_tile_map(item & tmask, NB, a.c, a.p);
+  size_t voff = size_t(item >> a.tile_bits) * a.vstride;
   C pf[NPT];
 #pragma unroll
-  for (int i = 0; i < NPT; ++i) pf[i] = xin[tm.g(tid + i * T)];
+  for (int i = 0; i < NPT; ++i) pf[i] = xin[voff + tm.g(tid + i * T)];
   for (;;) {
 #pragma unroll
     for (int i = 0; i < NPT; ++i) lds[bw_phys(tid + i * T)] = pf[i];
     const unsigned nbid = bid + gridDim.x;
-    const bool more = nbid < ntiles;
+    const bool more = nbid < nitems;
     TileMap tn = tm;
+    size_t vn = voff;
     if (more) {
-      tn = make_tile_map(xcd_tile(nbid, ntiles), NB, a.c, a.p);
+      const uint32_t nitem = xcd_tile(nbid, nitems);
+      tn = make_tile_map(nitem & tmask, NB, a.c, a.p);
+      vn = size_t(nitem >> a.tile_bits) * a.vstride;
 #pragma unroll
-      for (int i = 0; i < NPT; ++i) pf[i] = xin[tn.g(tid + i * T)];
+      for (int i = 0; i < NPT; ++i) pf[i] = xin[vn + tn.g(tid + i * T)];
     }
     __syncthreads();
     for (int wi = 0; wi < a.nwin; ++wi) {
@@ -252,22 +259,23 @@ __global__ void __launch_bounds__(1 << TB)
       C x = lds[bw_phys(j)];
       if (a.flags & BW_ROT) x = cmul(x, rot);
       if constexpr (PSI) {
-        const C p = psi[tm.g(j)];
+        const C p = psi[voff + tm.g(j)];
         x = (a.flags & BW_PSI_COEF) ? cfma(p, pc, x) : cadd(x, p);
       }
-      xout[tm.g(j)] = x;
+      xout[voff + tm.g(j)] = x;
     }
     if (!more) break;
     __syncthreads();
     bid = nbid;
     tm = tn;
+    voff = vn;
   }
 }
 
 size_t bw_lds_bytes(int n, size_t elem) { return size_t((1 << n) + (1 << (n - 4 > 0 ? n - 4 : 0)) + 1) * elem; }
 
 template <typename Real, int WB, int TB, int NB, bool PSI>
-hipError_t launch_bw_pipe(const BwPassArgs& a, unsigned ntiles, hipStream_t s) {
+hipError_t launch_bw_pipe(const BwPassArgs& a, unsigned nitems, hipStream_t s) {
   static int wgs_per_pass = 0;  // resident workgroups per pass (CUs x workgroups per CU)
   const size_t shmem = bw_lds_bytes(NB, sizeof(cpx<Real>));
   auto kern = bw_pipe_kernel<Real, WB, TB, NB, PSI>;
@@ -285,14 +293,14 @@ hipError_t launch_bw_pipe(const BwPassArgs& a, unsigned ntiles, hipStream_t s) {
     if (e != hipSuccess) return e;
     wgs_per_pass = std::max(8, (cus * std::max(1, per_cu)) & ~7);
   }
-  const unsigned grid = std::min<unsigned>(ntiles, static_cast<unsigned>(wgs_per_pass));
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(1 << TB), shmem, s, a, ntiles, static_cast<const cpx<Real>*>(a.mats),
+  const unsigned grid = std::min<unsigned>(nitems, static_cast<unsigned>(wgs_per_pass));
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(1 << TB), shmem, s, a, nitems, static_cast<const cpx<Real>*>(a.mats),
                      a.wins, a.gates, static_cast<cpx<Real>*>(a.xout));
   return hipGetLastError();
 }
 
 template <typename Real, int WB, int TB>
-hipError_t launch_bw_t(const BwPassArgs& a, unsigned ntiles, hipStream_t s) {
+hipError_t launch_bw_t(const BwPassArgs& a, unsigned nitems, hipStream_t s) {
   const size_t shmem = bw_lds_bytes(a.n, sizeof(cpx<Real>));
   auto kern = bw_pass_kernel<Real, WB, TB>;
   if (shmem > 65536) {
@@ -300,31 +308,31 @@ hipError_t launch_bw_t(const BwPassArgs& a, unsigned ntiles, hipStream_t s) {
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(kern, dim3(ntiles), dim3(1 << TB), shmem, s, a, static_cast<const cpx<Real>*>(a.mats), a.wins,
+  hipLaunchKernelGGL(kern, dim3(nitems), dim3(1 << TB), shmem, s, a, static_cast<const cpx<Real>*>(a.mats), a.wins,
                      a.gates);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t bw_launch_pass(const BwPassArgs& a, bool c64_dt, int wb, unsigned ntiles, hipStream_t s) {
+hipError_t bw_launch_pass(const BwPassArgs& a, bool c64_dt, int wb, unsigned nitems, hipStream_t s) {
   if (c64_dt) {
     // pipelined persistent form when every workgroup gets several tiles
-    if (wb == 4 && ntiles >= 1024 && ntiles % 8 == 0 && (a.n == 13 || a.n == 14)) {
+    if (wb == 4 && nitems >= 1024 && nitems % 8 == 0 && (a.n == 13 || a.n == 14)) {
       const bool ps = (a.flags & BW_ADD_PSI) != 0;
       if (a.n == 13)
-        return ps ? launch_bw_pipe<float, 4, 9, 13, true>(a, ntiles, s) : launch_bw_pipe<float, 4, 9, 13, false>(a, ntiles, s);
-      return ps ? launch_bw_pipe<float, 4, 9, 14, true>(a, ntiles, s) : launch_bw_pipe<float, 4, 9, 14, false>(a, ntiles, s);
+        return ps ? launch_bw_pipe<float, 4, 9, 13, true>(a, nitems, s) : launch_bw_pipe<float, 4, 9, 13, false>(a, nitems, s);
+      return ps ? launch_bw_pipe<float, 4, 9, 14, true>(a, nitems, s) : launch_bw_pipe<float, 4, 9, 14, false>(a, nitems, s);
     }
-    if (wb == 4) return a.n >= 12 ? launch_bw_t<float, 4, 9>(a, ntiles, s) : launch_bw_t<float, 4, 8>(a, ntiles, s);
-    if (wb == 3) return launch_bw_t<float, 3, 8>(a, ntiles, s);
-    if (wb == 2) return launch_bw_t<float, 2, 8>(a, ntiles, s);
+    if (wb == 4) return a.n >= 12 ? launch_bw_t<float, 4, 9>(a, nitems, s) : launch_bw_t<float, 4, 8>(a, nitems, s);
+    if (wb == 3) return launch_bw_t<float, 3, 8>(a, nitems, s);
+    if (wb == 2) return launch_bw_t<float, 2, 8>(a, nitems, s);
   } else {
     // complex128: 2^13-amplitude tiles (128 KB of LDS, one workgroup per CU)
     // take 512 threads (the pipelined form would spill registers)
-    if (wb == 4) return a.n >= 13 ? launch_bw_t<double, 4, 9>(a, ntiles, s) : launch_bw_t<double, 4, 8>(a, ntiles, s);
-    if (wb == 3) return launch_bw_t<double, 3, 8>(a, ntiles, s);
-    if (wb == 2) return launch_bw_t<double, 2, 8>(a, ntiles, s);
+    if (wb == 4) return a.n >= 13 ? launch_bw_t<double, 4, 9>(a, nitems, s) : launch_bw_t<double, 4, 8>(a, nitems, s);
+    if (wb == 3) return launch_bw_t<double, 3, 8>(a, nitems, s);
+    if (wb == 2) return launch_bw_t<double, 2, 8>(a, nitems, s);
   }
   return hipErrorInvalidValue;
 }
@@ -426,6 +434,7 @@ struct BwProgram {
     BwGate* gates = nullptr;
     int nwin = 0;
   };
+  int L = 0;  // amplitudes per vector: 2^L
   int npass = 0;
   Pass pass[2];  // [0] applied first (right block), [1] second (left block)
   void* mats = nullptr;  // 16-entry matrices, complex64 or complex128 (rounded once)
@@ -484,6 +493,7 @@ fq_status build_program(floquet_op* op, bool c64_dt, std::shared_ptr<BwProgram>*
   const int L = op->L;
   auto prog = std::make_shared<BwProgram>();
   prog->c64 = c64_dt;
+  prog->L = L;
   const std::vector<GateRef> refs = gate_refs(op);
   // matrices: each padded to 16 complex (one-site gates use the first 4)
   std::vector<c128> mats;
@@ -611,13 +621,17 @@ fq_status build_program(floquet_op* op, bool c64_dt, std::shared_ptr<BwProgram>*
   return FQ_OK;
 }
 
+// One pass over nvec vectors (at stride 2^L), in launches of at most 2^22
+// (vector, tile) items (a dispatch holds fewer than 2^32 work-items).
 fq_status run_pass(const BwProgram& prog, int which, const void* in, void* out, const void* psi, int flags,
-                   zd rot, zd psi_coef, hipStream_t s) {
+                   zd rot, zd psi_coef, int nvec, hipStream_t s) {
   const BwProgram::Pass& ps = prog.pass[which];
+  const size_t d = size_t(1) << prog.L;
+  const size_t bytes = d * (prog.c64 ? sizeof(c64) : sizeof(c128));
+  int tile_bits = 0;
+  while ((1u << tile_bits) < ps.ntiles) ++tile_bits;
+  const int per_launch = std::max(1, std::min(nvec, static_cast<int>((1u << 22) >> tile_bits)));
   BwPassArgs a{};
-  a.xin = in;
-  a.xout = out;
-  a.psi = psi;
   a.mats = prog.mats;
   a.wins = ps.wins;
   a.gates = ps.gates;
@@ -630,10 +644,19 @@ fq_status run_pass(const BwProgram& prog, int which, const void* in, void* out, 
   a.rot_im = rot.imag();
   a.psi_coef_re = psi_coef.real();
   a.psi_coef_im = psi_coef.imag();
-  hipError_t e = bw_launch_pass(a, prog.c64, ps.wb, ps.ntiles, s);
-  if (e != hipSuccess) {
-    set_error(std::string("brickwork pass launch failed: ") + hipGetErrorString(e));
-    return FQ_EDEVICE;
+  a.tile_bits = tile_bits;
+  a.vstride = d;
+  for (int v0 = 0; v0 < nvec; v0 += per_launch) {
+    const int nv = std::min(per_launch, nvec - v0);
+    const size_t off = size_t(v0) * bytes;
+    a.xin = static_cast<const char*>(in) + off;
+    a.xout = static_cast<char*>(out) + off;
+    a.psi = psi ? static_cast<const char*>(psi) + off : nullptr;
+    hipError_t e = bw_launch_pass(a, prog.c64, ps.wb, ps.ntiles * static_cast<unsigned>(nv), s);
+    if (e != hipSuccess) {
+      set_error(std::string("brickwork pass launch failed: ") + hipGetErrorString(e));
+      return FQ_EDEVICE;
+    }
   }
   return FQ_OK;
 }
@@ -684,7 +707,7 @@ fq_status bw_apply_U(floquet_op* op, fq_dtype dt, const void* psi, void* out, hi
   const BwProgram& prog = *pp;
   const void* in = psi;
   for (int i = 0; i < prog.npass; ++i) {
-    fq_status st = run_pass(prog, i, in, out, nullptr, 0, zd(1, 0), zd(1, 0), s);
+    fq_status st = run_pass(prog, i, in, out, nullptr, 0, zd(1, 0), zd(1, 0), 1, s);
     if (st != FQ_OK) return st;
     in = out;
   }
@@ -692,17 +715,22 @@ fq_status bw_apply_U(floquet_op* op, fq_dtype dt, const void* psi, void* out, hi
 }
 
 // Horner: w = a_k psi; k times w <- a psi + rot * U w (rot = e^{-i phi} for
-// the geometric sum, 1 for a general polynomial).
+// the geometric sum, 1 for a general polynomial), for nvec vectors at stride
+// 2^L, every pass one launch for all of them.
 fq_status bw_filter(floquet_op* op, int k, double phi, const zd* coefs, fq_dtype dt, const void* psi, void* out,
-                    hipStream_t s) {
+                    hipStream_t s, int nvec) {
   const BwProgram* pp = program_for(op, dt);
   if (!pp) return FQ_EINVAL;
   const BwProgram& prog = *pp;
   const zd rot = coefs ? zd(1, 0) : std::polar(1.0, -phi);
   const zd a_k = coefs ? coefs[k] : zd(1, 0);
   if (a_k != zd(1, 0)) {
-    fq_status st = poly_scale_copy(op, a_k, dt, psi, out, s);
-    if (st != FQ_OK) return st;
+    const size_t bytes = op->dim() * (dt == FQ_C64 ? sizeof(c64) : sizeof(c128));
+    for (int v = 0; v < nvec; ++v) {
+      fq_status st = poly_scale_copy(op, a_k, dt, static_cast<const char*>(psi) + size_t(v) * bytes,
+                                     static_cast<char*>(out) + size_t(v) * bytes, s);
+      if (st != FQ_OK) return st;
+    }
   }
   for (int step = 1; step <= k; ++step) {
     const void* in = (step == 1 && a_k == zd(1, 0)) ? psi : out;
@@ -710,7 +738,7 @@ fq_status bw_filter(floquet_op* op, int k, double phi, const zd* coefs, fq_dtype
     const int last_flags = BW_ROT | BW_ADD_PSI | (c != zd(1, 0) ? BW_PSI_COEF : 0);
     for (int i = 0; i < prog.npass; ++i) {
       const bool last = i == prog.npass - 1;
-      fq_status st = run_pass(prog, i, i == 0 ? in : out, out, psi, last ? last_flags : 0, rot, c, s);
+      fq_status st = run_pass(prog, i, i == 0 ? in : out, out, psi, last ? last_flags : 0, rot, c, nvec, s);
       if (st != FQ_OK) return st;
     }
   }

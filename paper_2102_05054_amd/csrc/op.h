@@ -116,7 +116,7 @@ fq_status filter_mixed(floquet_op* op, int k, double phi, const zd* coefs, fq_dt
                        void* out64, hipStream_t s);
 fq_status ensure_scratch32(floquet_op* op);
 // out_j = g_k(U) psi_j for n vectors (vector j at offset j*d of psi / out), in dt;
-// kicked Ising: one launch per Horner pass for all n vectors
+// one launch per Horner pass for all n vectors
 fq_status filter_many(floquet_op* op, int k, double phi, fq_dtype dt, int n, const void* psi, void* out,
                       hipStream_t s);
 // out = a * psi
@@ -126,7 +126,8 @@ fq_status poly_scale_copy(floquet_op* op, zd a, fq_dtype dt, const void* psi, vo
 fq_status bw_create(floquet_op* op);
 void bw_destroy(floquet_op* op);
 fq_status bw_apply_U(floquet_op* op, fq_dtype dt, const void* psi, void* out, hipStream_t s);
+// nvec vectors at stride 2^L, one launch per pass for all of them
 fq_status bw_filter(floquet_op* op, int k, double phi, const zd* coefs, fq_dtype dt, const void* psi,
-                    void* out, hipStream_t s);
+                    void* out, hipStream_t s, int nvec = 1);
 
 }  // namespace fq

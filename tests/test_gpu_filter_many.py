@@ -4,9 +4,9 @@ launch per Horner pass for all of them) against the oracle's geometric sum."""
 import numpy as np
 import pytest
 
-from gpu_util import bw_op, ki_op, rel, require_gpu, say, to_dev, to_np
+from gpu_util import bw_op, circ_op, ki_op, rel, require_gpu, say, to_dev, to_np
 from oracle import filters, models
-from workloads import brickwork, kicked_ising, random_state
+from workloads import brickwork, circuit, kicked_ising, random_state
 
 pytestmark = pytest.mark.gpu
 
@@ -42,7 +42,8 @@ def test_filter_many_kicked_ising(dt, L, n, k, phi):
 
 
 def test_filter_many_copy_single_vector_and_brickwork():
-    # k = 0 copies; one vector and brickwork ops take the one-by-one path
+    # k = 0 copies; one vector takes the single-vector path; a small
+    # brickwork op takes its one-tile pass with one workgroup per vector
     torch = require_gpu()
     p = kicked_ising(10, 3)
     psi = random_state(2 ** 10, 4, 3)
@@ -91,4 +92,39 @@ def test_filter_many_many_vectors_and_order_one(dt, L, n, k):
         out = to_np(op.apply_filter_many(to_dev(psi, _dt(dt)), k, 2.9))
     for j in (0, n // 2, n - 1):
         ref = filters.geometric_sum(lambda v: models.ki_apply(p, v), psi[j], k, 2.9)
+        assert rel(out[j], ref) < _tol(dt, k), j
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("L,n,k,phi", [(7, 5, 6, 0.9), (13, 3, 4, 2.2), (14, 4, 5, 0.4), (17, 2, 3, 1.5),
+                                       (18, 64, 1, 3.3)])
+def test_filter_many_brickwork(dt, L, n, k, phi):
+    # brickwork: one launch per pass for all vectors, items = (vector, tile);
+    # L = 7, 13 one tile per vector (complex128 splits L = 13), L = 14, 17
+    # two passes, L = 18 with 64 vectors the persistent complex64 form
+    say(f"apply_filter_many brickwork L={L} n={n} k={k} {dt}")
+    p = brickwork(L, 940 + L)
+    psi = random_state(2 ** L, 70 + L, n)
+    mv = (lambda v, U=models.dense(p): U @ v) if L <= 10 else (lambda v: models.bw_apply(p, v))
+    with bw_op(p) as op:
+        dpsi = to_dev(psi, _dt(dt))
+        out = to_np(op.apply_filter_many(dpsi, k, phi))
+        one = to_np(op.apply_filter(dpsi[n - 1], k, phi))
+    assert rel(out[n - 1], one) < (1e-14 if dt == "c128" else 1e-6)
+    for j in sorted({0, n // 2, n - 1}):
+        ref = filters.geometric_sum(mv, psi[j], k, phi)
+        assert rel(out[j], ref) < _tol(dt, k), j
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_filter_many_circuit(dt):
+    # a general circuit (gates in any order) through the same multi-vector passes
+    L, n, k = 15, 3, 4
+    say(f"apply_filter_many circuit L={L} n={n} k={k} {dt}")
+    p = circuit(L, 960, depth=4)
+    psi = random_state(2 ** L, 80, n)
+    with circ_op(p) as op:
+        out = to_np(op.apply_filter_many(to_dev(psi, _dt(dt)), k, 0.6))
+    for j in range(n):
+        ref = filters.geometric_sum(lambda v: models.circuit_apply(p, v), psi[j], k, 0.6)
         assert rel(out[j], ref) < _tol(dt, k), j
