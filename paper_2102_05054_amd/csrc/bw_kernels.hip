@@ -143,6 +143,25 @@ __device__ __forceinline__ void window_gates(cpx<Real> (&v)[1 << WB], const WinU
   if (w.count > 1) apply_gate<Real, WB>(v, wg.g1.kind, wg.g1.l, wg.m1);
 }
 
+// The same with one matrix live at a time, each read (scalar loads, served
+// by the scalar cache) just before its gate.  A complex128 matrix takes 64
+// scalar registers: holding both across the window spills scalar registers
+// into vector lanes, and every matrix use then costs a lane read.
+template <typename Real, int WB>
+__device__ __forceinline__ void window_gates_seq(cpx<Real> (&v)[1 << WB], const WinU& w, const GateU& g0,
+                                                 const GateU& g1, const cpx<Real>* __restrict__ mats) {
+  cpx<Real> m[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) m[i] = mats[16 * g0.mat + i];
+  apply_gate<Real, WB>(v, g0.kind, g0.l, m);
+  if (w.count > 1) {
+    asm volatile("" ::: "memory");  // keeps the second matrix's loads after the first gate
+#pragma unroll
+    for (int i = 0; i < 16; ++i) m[i] = mats[16 * g1.mat + i];
+    apply_gate<Real, WB>(v, g1.kind, g1.l, m);
+  }
+}
+
 template <typename Real, int WB, int TB>
 __global__ void __launch_bounds__(1 << TB)
     bw_pass_kernel(BwPassArgs a, const cpx<Real>* __restrict__ mats, const BwWin* __restrict__ wins,
@@ -161,10 +180,18 @@ __global__ void __launch_bounds__(1 << TB)
   for (int j = tid; j < N; j += T) lds[bw_phys(j)] = xin[tm.g(j)];
   __syncthreads();
   const int ngroups = N >> WB;
+  // complex128 with 16-amplitude windows: one live matrix (see window_gates_seq)
+  constexpr bool kSeq = sizeof(Real) == 8 && WB >= 4;
   for (int wi = 0; wi < a.nwin; ++wi) {
     const WinU w = load_win(wins + wi);
     WinGates<Real> wg;
-    load_win_gates<Real>(wg, w, gates, mats);
+    GateU g0{}, g1{};
+    if constexpr (kSeq) {
+      g0 = load_gate(gates + w.first);
+      if (w.count > 1) g1 = load_gate(gates + w.first + 1);
+    } else {
+      load_win_gates<Real>(wg, w, gates, mats);
+    }
     const uint32_t below = (1u << w.b) - 1u;
     for (int g = tid; g < ngroups; g += T) {
       // insert WB zero bits at position b
@@ -172,7 +199,10 @@ __global__ void __launch_bounds__(1 << TB)
       C v[1 << WB];
 #pragma unroll
       for (int m = 0; m < (1 << WB); ++m) v[m] = lds[bw_phys(base + (m << w.b))];
-      window_gates<Real, WB>(v, w, wg);
+      if constexpr (kSeq)
+        window_gates_seq<Real, WB>(v, w, g0, g1, mats);
+      else
+        window_gates<Real, WB>(v, w, wg);
 #pragma unroll
       for (int m = 0; m < (1 << WB); ++m) lds[bw_phys(base + (m << w.b))] = v[m];
     }
@@ -203,6 +233,7 @@ __global__ void __launch_bounds__(1 << TB)
   constexpr int T = 1 << TB, N = 1 << NB, NPT = N / T;
   constexpr int GPT = 1 << (NB - WB - TB);  // window groups per thread
   static_assert(NB - WB >= TB, "every thread owns a window group");
+  constexpr bool kSeq = sizeof(Real) == 8 && WB >= 4;  // see window_gates_seq
   extern __shared__ char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
   const int tid = threadIdx.x;
@@ -238,7 +269,13 @@ __global__ void __launch_bounds__(1 << TB)
     for (int wi = 0; wi < a.nwin; ++wi) {
       const WinU w = load_win(wins + wi);
       WinGates<Real> wg;
-      load_win_gates<Real>(wg, w, gates, mats);
+      GateU g0{}, g1{};
+      if constexpr (kSeq) {
+        g0 = load_gate(gates + w.first);
+        if (w.count > 1) g1 = load_gate(gates + w.first + 1);
+      } else {
+        load_win_gates<Real>(wg, w, gates, mats);
+      }
       const uint32_t below = (1u << w.b) - 1u;
 #pragma unroll 1
       for (int gi = 0; gi < GPT; ++gi) {
@@ -247,7 +284,10 @@ __global__ void __launch_bounds__(1 << TB)
         C v[1 << WB];
 #pragma unroll
         for (int m = 0; m < (1 << WB); ++m) v[m] = lds[bw_phys(base + (m << w.b))];
-        window_gates<Real, WB>(v, w, wg);
+        if constexpr (kSeq)
+          window_gates_seq<Real, WB>(v, w, g0, g1, mats);
+        else
+          window_gates<Real, WB>(v, w, wg);
 #pragma unroll
         for (int m = 0; m < (1 << WB); ++m) lds[bw_phys(base + (m << w.b))] = v[m];
       }
@@ -274,12 +314,14 @@ __global__ void __launch_bounds__(1 << TB)
 
 size_t bw_lds_bytes(int n, size_t elem) { return size_t((1 << n) + (1 << (n - 4 > 0 ? n - 4 : 0)) + 1) * elem; }
 
+// Resident workgroups of a pipelined pass (CUs x workgroups per CU, a
+// multiple of 8), computed once per kernel.
 template <typename Real, int WB, int TB, int NB, bool PSI>
-hipError_t launch_bw_pipe(const BwPassArgs& a, unsigned nitems, hipStream_t s) {
-  static int wgs_per_pass = 0;  // resident workgroups per pass (CUs x workgroups per CU)
-  const size_t shmem = bw_lds_bytes(NB, sizeof(cpx<Real>));
-  auto kern = bw_pipe_kernel<Real, WB, TB, NB, PSI>;
+hipError_t pipe_slots(int* slots) {
+  static int wgs_per_pass = 0;
   if (wgs_per_pass == 0) {
+    const size_t shmem = bw_lds_bytes(NB, sizeof(cpx<Real>));
+    auto kern = bw_pipe_kernel<Real, WB, TB, NB, PSI>;
     if (shmem > 65536) {
       hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem));
@@ -293,9 +335,19 @@ hipError_t launch_bw_pipe(const BwPassArgs& a, unsigned nitems, hipStream_t s) {
     if (e != hipSuccess) return e;
     wgs_per_pass = std::max(8, (cus * std::max(1, per_cu)) & ~7);
   }
-  const unsigned grid = std::min<unsigned>(nitems, static_cast<unsigned>(wgs_per_pass));
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(1 << TB), shmem, s, a, nitems, static_cast<const cpx<Real>*>(a.mats),
-                     a.wins, a.gates, static_cast<cpx<Real>*>(a.xout));
+  *slots = wgs_per_pass;
+  return hipSuccess;
+}
+
+template <typename Real, int WB, int TB, int NB, bool PSI>
+hipError_t launch_bw_pipe(const BwPassArgs& a, unsigned nitems, hipStream_t s) {
+  int slots = 0;
+  hipError_t e = pipe_slots<Real, WB, TB, NB, PSI>(&slots);
+  if (e != hipSuccess) return e;
+  const size_t shmem = bw_lds_bytes(NB, sizeof(cpx<Real>));
+  const unsigned grid = std::min<unsigned>(nitems, static_cast<unsigned>(slots));
+  hipLaunchKernelGGL((bw_pipe_kernel<Real, WB, TB, NB, PSI>), dim3(grid), dim3(1 << TB), shmem, s, a, nitems,
+                     static_cast<const cpx<Real>*>(a.mats), a.wins, a.gates, static_cast<cpx<Real>*>(a.xout));
   return hipGetLastError();
 }
 
@@ -315,24 +367,56 @@ hipError_t launch_bw_t(const BwPassArgs& a, unsigned nitems, hipStream_t s) {
 
 }  // namespace
 
+// Tile kernels take one thread per window group (2^(n - wb) of them, at
+// least one wave): with more threads than groups the extra lanes idle through
+// every window.  Launches too small to give every SIMD a wave that way take
+// larger workgroups (up to 256 threads, 512 for 2^13-amplitude and larger
+// tiles, and for complex64 2^12), whose extra threads still share the tile's
+// loads and stores.
 hipError_t bw_launch_pass(const BwPassArgs& a, bool c64_dt, int wb, unsigned nitems, hipStream_t s) {
+  // the pipelined persistent form when every workgroup gets several tiles:
+  // complex64 2^13 / 2^14 tiles (512 threads); complex128 2^11 / 2^12 tiles
+  // (one thread per window group) when a workgroup gets two (measured at
+  // L = 20: 4 vectors 32.9 against 36.4 us per U and vector; with 8 vectors,
+  // four tiles per workgroup, the one-tile workgroups are faster, 33.3
+  // against 36.7 us)
+  const bool ps = (a.flags & BW_ADD_PSI) != 0;
+  if (c64_dt && wb == 4 && nitems >= 1024 && nitems % 8 == 0 && (a.n == 13 || a.n == 14)) {
+    if (a.n == 13)
+      return ps ? launch_bw_pipe<float, 4, 9, 13, true>(a, nitems, s) : launch_bw_pipe<float, 4, 9, 13, false>(a, nitems, s);
+    return ps ? launch_bw_pipe<float, 4, 9, 14, true>(a, nitems, s) : launch_bw_pipe<float, 4, 9, 14, false>(a, nitems, s);
+  }
+  int slots = 0;
+  if (!c64_dt && wb == 4 && nitems >= 1024 && nitems % 8 == 0 && (a.n == 11 || a.n == 12)) {
+    hipError_t e = a.n == 11 ? pipe_slots<double, 4, 7, 11, true>(&slots) : pipe_slots<double, 4, 8, 12, true>(&slots);
+    if (e != hipSuccess) return e;
+  }
+  if (slots > 0 && nitems <= 2u * static_cast<unsigned>(slots)) {
+    if (a.n == 11)
+      return ps ? launch_bw_pipe<double, 4, 7, 11, true>(a, nitems, s) : launch_bw_pipe<double, 4, 7, 11, false>(a, nitems, s);
+    return ps ? launch_bw_pipe<double, 4, 8, 12, true>(a, nitems, s) : launch_bw_pipe<double, 4, 8, 12, false>(a, nitems, s);
+  }
+  const int tb_max = (a.n >= 13 || (c64_dt && a.n >= 12)) ? 9 : 8;
+  int tb = std::max(6, std::min(tb_max, a.n - wb));
+  while (tb < tb_max && (static_cast<uint64_t>(nitems) << (tb - 6)) < 1024u) ++tb;
   if (c64_dt) {
-    // pipelined persistent form when every workgroup gets several tiles
-    if (wb == 4 && nitems >= 1024 && nitems % 8 == 0 && (a.n == 13 || a.n == 14)) {
-      const bool ps = (a.flags & BW_ADD_PSI) != 0;
-      if (a.n == 13)
-        return ps ? launch_bw_pipe<float, 4, 9, 13, true>(a, nitems, s) : launch_bw_pipe<float, 4, 9, 13, false>(a, nitems, s);
-      return ps ? launch_bw_pipe<float, 4, 9, 14, true>(a, nitems, s) : launch_bw_pipe<float, 4, 9, 14, false>(a, nitems, s);
+    if (wb == 4) {
+      if (tb == 9) return launch_bw_t<float, 4, 9>(a, nitems, s);
+      if (tb == 8) return launch_bw_t<float, 4, 8>(a, nitems, s);
+      if (tb == 7) return launch_bw_t<float, 4, 7>(a, nitems, s);
+      return launch_bw_t<float, 4, 6>(a, nitems, s);
     }
-    if (wb == 4) return a.n >= 12 ? launch_bw_t<float, 4, 9>(a, nitems, s) : launch_bw_t<float, 4, 8>(a, nitems, s);
-    if (wb == 3) return launch_bw_t<float, 3, 8>(a, nitems, s);
-    if (wb == 2) return launch_bw_t<float, 2, 8>(a, nitems, s);
+    if (wb == 3) return launch_bw_t<float, 3, 6>(a, nitems, s);
+    if (wb == 2) return launch_bw_t<float, 2, 6>(a, nitems, s);
   } else {
-    // complex128: 2^13-amplitude tiles (128 KB of LDS, one workgroup per CU)
-    // take 512 threads (the pipelined form would spill registers)
-    if (wb == 4) return a.n >= 13 ? launch_bw_t<double, 4, 9>(a, nitems, s) : launch_bw_t<double, 4, 8>(a, nitems, s);
-    if (wb == 3) return launch_bw_t<double, 3, 8>(a, nitems, s);
-    if (wb == 2) return launch_bw_t<double, 2, 8>(a, nitems, s);
+    if (wb == 4) {
+      if (tb == 9) return launch_bw_t<double, 4, 9>(a, nitems, s);
+      if (tb == 8) return launch_bw_t<double, 4, 8>(a, nitems, s);
+      if (tb == 7) return launch_bw_t<double, 4, 7>(a, nitems, s);
+      return launch_bw_t<double, 4, 6>(a, nitems, s);
+    }
+    if (wb == 3) return launch_bw_t<double, 3, 6>(a, nitems, s);
+    if (wb == 2) return launch_bw_t<double, 2, 6>(a, nitems, s);
   }
   return hipErrorInvalidValue;
 }

@@ -97,11 +97,12 @@ def test_filter_many_many_vectors_and_order_one(dt, L, n, k):
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
 @pytest.mark.parametrize("L,n,k,phi", [(7, 5, 6, 0.9), (13, 3, 4, 2.2), (14, 4, 5, 0.4), (17, 2, 3, 1.5),
-                                       (18, 64, 1, 3.3)])
+                                       (18, 64, 1, 3.3), (20, 4, 2, 0.8)])
 def test_filter_many_brickwork(dt, L, n, k, phi):
     # brickwork: one launch per pass for all vectors, items = (vector, tile);
     # L = 7, 13 one tile per vector (complex128 splits L = 13), L = 14, 17
-    # two passes, L = 18 with 64 vectors the persistent complex64 form
+    # two passes, L = 18 with 64 vectors and L = 20 with 4 the persistent
+    # pipelined forms (complex64 2^13 / 2^14 tiles, complex128 2^11 / 2^12)
     say(f"apply_filter_many brickwork L={L} n={n} k={k} {dt}")
     p = brickwork(L, 940 + L)
     psi = random_state(2 ** L, 70 + L, n)
