@@ -66,6 +66,9 @@ def parse():
     ap.add_argument("--workload", default="ki_L20", choices=["ki_L20", "ki_batched", "bw_L24", "bw_paper"],
                     help="ki_batched: 256 realisations x 4 targets, L in 12..16, one batched call; "
                          "bw_L24: the brickwork filter (k=300) at L=24")
+    ap.add_argument("--filter-steps", type=int, default=0,
+                    help="bw_paper: time only the block filter (--block-c128 vectors per launch, this many Horner "
+                         "steps) instead of the solve")
     ap.add_argument("--profile-gemm", action="store_true",
                     help="only solves with filter order 1 (two restarts each), for counter runs of the FP64 "
                          "matrix-core basis rotation")
@@ -412,6 +415,9 @@ def brickwork_paper(args):
     k = int(math.floor(0.8 * 2 ** (L + 1) / ncv))
     p = bw_params(L, 5000 + L)
     op = brickwork(L, p.gates)
+    if args.filter_steps > 0:
+        brickwork_block_filter(args, op, L)
+        return
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev, _, res, st, status = op.arnoldi_eigs(nev, 0.0, k=k, ncv=ncv, tol=1e-10, max_restarts=args.max_restarts,
@@ -436,6 +442,42 @@ def brickwork_paper(args):
         "ratio_paper_cpu_over_this": (paper / dt) if paper else None,
     }
     print(json.dumps(line))
+
+
+def brickwork_block_filter(args, op, L):
+    """The filter of the paper's benchmark solve alone: apply_filter_many on
+    --block-c128 complex128 vectors (one launch per pass for all of them),
+    --filter-steps Horner steps, timed with HIP events on the stream the
+    passes run on.  Flops as for the L = 24 filter (32 * L * d per U); the FP64
+    vector peak is 78.6 TFLOP/s."""
+    import torch
+
+    from workloads import random_state
+    d, b, k = 2 ** L, args.block_c128, args.filter_steps
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        x = torch.from_numpy(random_state(d, 7, b)).to("cuda", torch.complex128).contiguous()
+        y = torch.empty_like(x)
+        op.apply_filter_many(x, 2, 0.0, out=y, stream=s)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        op.apply_filter_many(x, k, 0.0, out=y, stream=s)
+        e1.record(s)
+        s.synchronize()
+    op.close()
+    us_u = 1e3 * e0.elapsed_time(e1) / (k * b)
+    tf = 32 * L * d / (us_u * 1e6)
+    print(json.dumps({
+        "metric": "U-applications/s of the block brickwork filter of the paper's benchmark",
+        "value": 1e6 / us_u, "unit": "U-applications/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": e0.elapsed_time(e1), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c128", "data": "synthetic (seeded Haar-random two-site gates)",
+        "config": {"workload": f"brickwork Haar circuit L={L}, {b} vectors per launch, {k} Horner steps",
+                   "L": L, "block": b, "k": k},
+        "us_per_U": us_u,
+        "roofline": {"bound": "alu", "achieved": tf, "peak": 78.6, "unit": "TFLOP/s", "frac": tf / 78.6,
+                     "traffic": None, "hbm_GBs": 5 * d * 16 / (us_u * 1e3)},
+    }))
 
 
 def cpu_baseline(p, seconds=15.0):
