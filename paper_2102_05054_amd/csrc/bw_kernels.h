@@ -20,6 +20,9 @@ struct BwGate {
 };
 static_assert(sizeof(BwGate) == 4, "BwGate is read as one 32-bit word");
 
+// Gates per window at most (the kernels apply them one matrix at a time).
+constexpr size_t kBwWindowGates = 8;
+
 // One window: the gates gates[first .. first + count) act inside tile bits
 // [b, b + WB) and are applied in this order, with the window's 2^WB
 // amplitudes held in registers (one LDS round trip per window).

@@ -13,10 +13,10 @@
 // psi, write w).  Inside a tile the gates are applied in windows of WB
 // consecutive tile bits: each thread takes the 2^WB amplitudes of one window
 // group from LDS into registers, applies the window's gates in order, and
-// writes them back.  A host scheduler fills each window with up to two gates
-// of either layer whose bits lie inside it and whose earlier gates on the
-// same sites are done, so any order of local gates (more layers, other gate
-// sets) maps onto the same windows.
+// writes them back.  A host scheduler fills each window with up to eight
+// gates of either layer whose bits lie inside it and whose earlier gates on
+// the same sites are done, so any order of local gates (more layers, other
+// gate sets) maps onto the same windows.
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -115,50 +115,24 @@ __device__ __forceinline__ GateU load_gate(const BwGate* p) {
   return g;
 }
 
-// The (at most two) gates of a window with their matrices, read once per
-// window before the group loop (scalar loads).
-template <typename Real>
-struct WinGates {
-  GateU g0, g1;
-  cpx<Real> m0[16], m1[16];
-};
-
-template <typename Real>
-__device__ __forceinline__ void load_win_gates(WinGates<Real>& wg, const WinU& w, const BwGate* __restrict__ gates,
-                                               const cpx<Real>* __restrict__ mats) {
-  wg.g0 = load_gate(gates + w.first);
-#pragma unroll
-  for (int i = 0; i < 16; ++i) wg.m0[i] = mats[16 * wg.g0.mat + i];
-  if (w.count > 1) {
-    wg.g1 = load_gate(gates + w.first + 1);
-#pragma unroll
-    for (int i = 0; i < 16; ++i) wg.m1[i] = mats[16 * wg.g1.mat + i];
-  }
-}
-
-// Apply the window's gates to the group of 2^WB amplitudes held in v.
+// Apply the window's gates, in order, to the group of 2^WB amplitudes held in
+// v, with one matrix live at a time, read (scalar loads, served by the scalar
+// cache) just before its gate.  A complex128 matrix takes 64 scalar
+// registers: holding two or more across the window spills scalar registers
+// into vector lanes, where every matrix use costs a lane read; one at a time,
+// a window can take any number of gates, and fewer windows mean fewer LDS
+// round trips.
 template <typename Real, int WB>
-__device__ __forceinline__ void window_gates(cpx<Real> (&v)[1 << WB], const WinU& w, const WinGates<Real>& wg) {
-  apply_gate<Real, WB>(v, wg.g0.kind, wg.g0.l, wg.m0);
-  if (w.count > 1) apply_gate<Real, WB>(v, wg.g1.kind, wg.g1.l, wg.m1);
-}
-
-// The same with one matrix live at a time, each read (scalar loads, served
-// by the scalar cache) just before its gate.  A complex128 matrix takes 64
-// scalar registers: holding both across the window spills scalar registers
-// into vector lanes, and every matrix use then costs a lane read.
-template <typename Real, int WB>
-__device__ __forceinline__ void window_gates_seq(cpx<Real> (&v)[1 << WB], const WinU& w, const GateU& g0,
-                                                 const GateU& g1, const cpx<Real>* __restrict__ mats) {
-  cpx<Real> m[16];
+__device__ __forceinline__ void window_gates(cpx<Real> (&v)[1 << WB], const WinU& w, const BwGate* __restrict__ gates,
+                                             const cpx<Real>* __restrict__ mats) {
+#pragma unroll 1
+  for (int q = 0; q < w.count; ++q) {
+    const GateU g = load_gate(gates + w.first + q);
+    cpx<Real> m[16];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) m[i] = mats[16 * g0.mat + i];
-  apply_gate<Real, WB>(v, g0.kind, g0.l, m);
-  if (w.count > 1) {
-    asm volatile("" ::: "memory");  // keeps the second matrix's loads after the first gate
-#pragma unroll
-    for (int i = 0; i < 16; ++i) m[i] = mats[16 * g1.mat + i];
-    apply_gate<Real, WB>(v, g1.kind, g1.l, m);
+    for (int i = 0; i < 16; ++i) m[i] = mats[16 * g.mat + i];
+    apply_gate<Real, WB>(v, g.kind, g.l, m);
+    asm volatile("" ::: "memory");  // keeps the next matrix's loads after this gate
   }
 }
 
@@ -180,18 +154,8 @@ __global__ void __launch_bounds__(1 << TB)
   for (int j = tid; j < N; j += T) lds[bw_phys(j)] = xin[tm.g(j)];
   __syncthreads();
   const int ngroups = N >> WB;
-  // complex128 with 16-amplitude windows: one live matrix (see window_gates_seq)
-  constexpr bool kSeq = sizeof(Real) == 8 && WB >= 4;
   for (int wi = 0; wi < a.nwin; ++wi) {
     const WinU w = load_win(wins + wi);
-    WinGates<Real> wg;
-    GateU g0{}, g1{};
-    if constexpr (kSeq) {
-      g0 = load_gate(gates + w.first);
-      if (w.count > 1) g1 = load_gate(gates + w.first + 1);
-    } else {
-      load_win_gates<Real>(wg, w, gates, mats);
-    }
     const uint32_t below = (1u << w.b) - 1u;
     for (int g = tid; g < ngroups; g += T) {
       // insert WB zero bits at position b
@@ -199,10 +163,7 @@ __global__ void __launch_bounds__(1 << TB)
       C v[1 << WB];
 #pragma unroll
       for (int m = 0; m < (1 << WB); ++m) v[m] = lds[bw_phys(base + (m << w.b))];
-      if constexpr (kSeq)
-        window_gates_seq<Real, WB>(v, w, g0, g1, mats);
-      else
-        window_gates<Real, WB>(v, w, wg);
+      window_gates<Real, WB>(v, w, gates, mats);
 #pragma unroll
       for (int m = 0; m < (1 << WB); ++m) lds[bw_phys(base + (m << w.b))] = v[m];
     }
@@ -233,7 +194,6 @@ __global__ void __launch_bounds__(1 << TB)
   constexpr int T = 1 << TB, N = 1 << NB, NPT = N / T;
   constexpr int GPT = 1 << (NB - WB - TB);  // window groups per thread
   static_assert(NB - WB >= TB, "every thread owns a window group");
-  constexpr bool kSeq = sizeof(Real) == 8 && WB >= 4;  // see window_gates_seq
   extern __shared__ char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
   const int tid = threadIdx.x;
@@ -268,14 +228,6 @@ __global__ void __launch_bounds__(1 << TB)
     __syncthreads();
     for (int wi = 0; wi < a.nwin; ++wi) {
       const WinU w = load_win(wins + wi);
-      WinGates<Real> wg;
-      GateU g0{}, g1{};
-      if constexpr (kSeq) {
-        g0 = load_gate(gates + w.first);
-        if (w.count > 1) g1 = load_gate(gates + w.first + 1);
-      } else {
-        load_win_gates<Real>(wg, w, gates, mats);
-      }
       const uint32_t below = (1u << w.b) - 1u;
 #pragma unroll 1
       for (int gi = 0; gi < GPT; ++gi) {
@@ -284,10 +236,7 @@ __global__ void __launch_bounds__(1 << TB)
         C v[1 << WB];
 #pragma unroll
         for (int m = 0; m < (1 << WB); ++m) v[m] = lds[bw_phys(base + (m << w.b))];
-        if constexpr (kSeq)
-          window_gates_seq<Real, WB>(v, w, g0, g1, mats);
-        else
-          window_gates<Real, WB>(v, w, wg);
+        window_gates<Real, WB>(v, w, gates, mats);
 #pragma unroll
         for (int m = 0; m < (1 << WB); ++m) lds[bw_phys(base + (m << w.b))] = v[m];
       }
@@ -374,27 +323,15 @@ hipError_t launch_bw_t(const BwPassArgs& a, unsigned nitems, hipStream_t s) {
 // tiles, and for complex64 2^12), whose extra threads still share the tile's
 // loads and stores.
 hipError_t bw_launch_pass(const BwPassArgs& a, bool c64_dt, int wb, unsigned nitems, hipStream_t s) {
-  // the pipelined persistent form when every workgroup gets several tiles:
-  // complex64 2^13 / 2^14 tiles (512 threads); complex128 2^11 / 2^12 tiles
-  // (one thread per window group) when a workgroup gets two (measured at
-  // L = 20: 4 vectors 32.9 against 36.4 us per U and vector; with 8 vectors,
-  // four tiles per workgroup, the one-tile workgroups are faster, 33.3
-  // against 36.7 us)
+  // complex64 2^13 / 2^14 tiles: the pipelined persistent form when every
+  // workgroup gets several tiles.  (The same form for complex128 2^11 / 2^12
+  // tiles lost to one-tile workgroups once the windows took up to eight
+  // gates: L = 20, 4 vectors, 32.5 against 31.1 us per U and vector.)
   const bool ps = (a.flags & BW_ADD_PSI) != 0;
   if (c64_dt && wb == 4 && nitems >= 1024 && nitems % 8 == 0 && (a.n == 13 || a.n == 14)) {
     if (a.n == 13)
       return ps ? launch_bw_pipe<float, 4, 9, 13, true>(a, nitems, s) : launch_bw_pipe<float, 4, 9, 13, false>(a, nitems, s);
     return ps ? launch_bw_pipe<float, 4, 9, 14, true>(a, nitems, s) : launch_bw_pipe<float, 4, 9, 14, false>(a, nitems, s);
-  }
-  int slots = 0;
-  if (!c64_dt && wb == 4 && nitems >= 1024 && nitems % 8 == 0 && (a.n == 11 || a.n == 12)) {
-    hipError_t e = a.n == 11 ? pipe_slots<double, 4, 7, 11, true>(&slots) : pipe_slots<double, 4, 8, 12, true>(&slots);
-    if (e != hipSuccess) return e;
-  }
-  if (slots > 0 && nitems <= 2u * static_cast<unsigned>(slots)) {
-    if (a.n == 11)
-      return ps ? launch_bw_pipe<double, 4, 7, 11, true>(a, nitems, s) : launch_bw_pipe<double, 4, 7, 11, false>(a, nitems, s);
-    return ps ? launch_bw_pipe<double, 4, 8, 12, true>(a, nitems, s) : launch_bw_pipe<double, 4, 8, 12, false>(a, nitems, s);
   }
   const int tb_max = (a.n >= 13 || (c64_dt && a.n >= 12)) ? 9 : 8;
   int tb = std::max(6, std::min(tb_max, a.n - wb));
@@ -462,9 +399,8 @@ struct PGate {
 // this one); gates on disjoint bits commute, so this reproduces the program.
 // The window starts at the first remaining gate's low bit or up to wb - 2
 // bits below it, whichever placement applies the most gates.
-void schedule_windows(const std::vector<PGate>& g, int n, int wb, std::vector<BwWin>* wins,
+void schedule_windows(const std::vector<PGate>& g, int n, int wb, size_t kMaxGates, std::vector<BwWin>* wins,
                       std::vector<BwGate>* out) {
-  constexpr size_t kMaxGates = 2;  // per window (the kernels hold two matrices)
   const size_t G = g.size();
   std::vector<char> done(G, 0);
   auto overlaps = [&](size_t i, size_t j) { return g[i].q < g[j].q + g[j].width && g[j].q < g[i].q + g[i].width; };
@@ -617,7 +553,8 @@ fq_status build_program(floquet_op* op, bool c64_dt, std::shared_ptr<BwProgram>*
   auto upload = [&](BwProgram::Pass& ps, const std::vector<PGate>& g) -> fq_status {
     std::vector<BwWin> wins;
     std::vector<BwGate> gl;
-    if (!g.empty()) schedule_windows(g, ps.n, ps.wb, &wins, &gl);
+    if (!g.empty())
+      schedule_windows(g, ps.n, ps.wb, kBwWindowGates, &wins, &gl);
     ps.nwin = static_cast<int>(wins.size());
     FQ_HIP_CHECK(hipMalloc(&ps.wins, std::max<size_t>(1, wins.size()) * sizeof(BwWin)));
     FQ_HIP_CHECK(hipMalloc(&ps.gates, std::max<size_t>(1, gl.size()) * sizeof(BwGate)));

@@ -101,8 +101,8 @@ def test_filter_many_many_vectors_and_order_one(dt, L, n, k):
 def test_filter_many_brickwork(dt, L, n, k, phi):
     # brickwork: one launch per pass for all vectors, items = (vector, tile);
     # L = 7, 13 one tile per vector (complex128 splits L = 13), L = 14, 17
-    # two passes, L = 18 with 64 vectors and L = 20 with 4 the persistent
-    # pipelined forms (complex64 2^13 / 2^14 tiles, complex128 2^11 / 2^12)
+    # two passes, L = 18 with 64 vectors and L = 20 with 4 (complex64: the
+    # persistent pipelined form for the 2^13 / 2^14 tiles)
     say(f"apply_filter_many brickwork L={L} n={n} k={k} {dt}")
     p = brickwork(L, 940 + L)
     psi = random_state(2 ** L, 70 + L, n)
