@@ -27,6 +27,10 @@ COMMON = [
     f"--offload-arch={ARCH}",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # std::complex products and quotients of the host-side dense algebra
+    # (Schur form of the projected matrix) inline as plain formulas instead of
+    # calls that rescale for infinities and NaNs; its entries are O(1)
+    "-fcx-limited-range",
     "-I", os.path.join(ROOT, "include"),
 ]
 
