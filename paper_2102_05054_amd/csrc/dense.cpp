@@ -50,9 +50,27 @@ void rot_cols(ZMat& A, int k, int i0, int i1, double c, zd s) {
   }
 }
 
+// A rotation of columns (k, k+1) of Z, recorded during the QR sweeps.
+struct ZRot {
+  int k;
+  double c;
+  zd s;
+};
+
+// Z <- Z G_1^H G_2^H ... for the recorded rotations in order.  Applied
+// after the iteration, a block of 32 rows of Z at a time (the block's two
+// columns of each rotation stay in cache across the rotations).
+void apply_z_rotations(ZMat& Z, const std::vector<ZRot>& rots) {
+  const int n = Z.n;
+  for (int r0 = 0; r0 < n; r0 += 32) {
+    const int r1 = r0 + 32 < n ? r0 + 32 : n;
+    for (const ZRot& g : rots) rot_cols(Z, g.k, r0, r1, g.c, g.s);
+  }
+}
+
 void hessenberg(ZMat& A, ZMat& Z) {
   const int n = A.n;
-  std::vector<zd> v(n);
+  std::vector<zd> v(n), p(n), q(n);
   for (int k = 0; k + 2 < n; ++k) {
     double xn = 0.0;
     for (int i = k + 1; i < n; ++i) xn += std::norm(A(i, k));
@@ -75,18 +93,28 @@ void hessenberg(ZMat& A, ZMat& Z) {
       s *= tau;
       for (int i = k + 1; i < n; ++i) A(i, j) -= v[i] * s;
     }
-    // A <- A P, Z <- Z P
+    // A <- A P, Z <- Z P, column by column (contiguous in memory):
+    // p = A v, q = Z v, then column j -= tau * conj(v_j) * p (resp. q)
     for (int i = 0; i < n; ++i) {
-      zd s = 0, t = 0;
-      for (int j = k + 1; j < n; ++j) {
-        s += A(i, j) * v[j];
-        t += Z(i, j) * v[j];
+      p[i] = 0;
+      q[i] = 0;
+    }
+    for (int j = k + 1; j < n; ++j) {
+      const zd vj = v[j];
+      const zd* a = &A(0, j);
+      const zd* z = &Z(0, j);
+      for (int i = 0; i < n; ++i) {
+        p[i] += a[i] * vj;
+        q[i] += z[i] * vj;
       }
-      s *= tau;
-      t *= tau;
-      for (int j = k + 1; j < n; ++j) {
-        A(i, j) -= s * std::conj(v[j]);
-        Z(i, j) -= t * std::conj(v[j]);
+    }
+    for (int j = k + 1; j < n; ++j) {
+      const zd f = tau * std::conj(v[j]);
+      zd* a = &A(0, j);
+      zd* z = &Z(0, j);
+      for (int i = 0; i < n; ++i) {
+        a[i] -= p[i] * f;
+        z[i] -= q[i] * f;
       }
     }
     for (int i = k + 2; i < n; ++i) A(i, k) = 0;
@@ -109,6 +137,10 @@ bool schur(ZMat& A, ZMat& Z) {
   int iter = 0;
   const int max_iter = 60 * n;
   int total = 0;
+  // Z does not enter the iteration: its rotations are recorded and applied
+  // once at the end
+  std::vector<ZRot> zrots;
+  zrots.reserve(size_t(n) * 8);
   while (hi > 0) {
     // find the start l of the unreduced block ending at hi
     int l = hi;
@@ -125,7 +157,10 @@ bool schur(ZMat& A, ZMat& Z) {
       iter = 0;
       continue;
     }
-    if (++total > max_iter) return false;
+    if (++total > max_iter) {
+      apply_z_rotations(Z, zrots);
+      return false;
+    }
     ++iter;
     // Wilkinson shift from the trailing 2x2 of the active block
     zd mu;
@@ -146,7 +181,7 @@ bool schur(ZMat& A, ZMat& Z) {
       givens(x, y, &c, &s);
       rot_rows(A, k, k > l ? k - 1 : l, n, c, s);
       rot_cols(A, k, 0, std::min(k + 3, hi + 1), c, s);
-      rot_cols(Z, k, 0, n, c, s);
+      zrots.push_back({k, c, s});
       if (k > l) A(k + 1, k - 1) = 0;
       if (k + 1 < hi) {
         x = A(k + 1, k);
@@ -154,6 +189,7 @@ bool schur(ZMat& A, ZMat& Z) {
       }
     }
   }
+  apply_z_rotations(Z, zrots);
   for (int j = 0; j < n; ++j)
     for (int i = j + 1; i < n; ++i) A(i, j) = 0;
   return true;

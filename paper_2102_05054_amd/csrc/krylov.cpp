@@ -643,18 +643,24 @@ fq_status fq_host_schur(int n, double* a_host, double* z_host, double* w_host) {
     return FQ_EINVAL;
   }
   ZMat A(n, n), Z;
-  for (size_t i = 0; i < size_t(n) * n; ++i) A.a[i] = zd(a_host[2 * i], a_host[2 * i + 1]);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+      const size_t e = size_t(j) * n + i;
+      A(i, j) = zd(a_host[2 * e], a_host[2 * e + 1]);
+    }
   if (!schur(A, Z)) {
     set_error("QR iteration did not converge");
     return FQ_ENUMERIC;
   }
   schur_sort(A, Z, n, [](const zd& x, const zd& y) { return std::abs(x) > std::abs(y); });
-  for (size_t i = 0; i < size_t(n) * n; ++i) {
-    a_host[2 * i] = A.a[i].real();
-    a_host[2 * i + 1] = A.a[i].imag();
-    z_host[2 * i] = Z.a[i].real();
-    z_host[2 * i + 1] = Z.a[i].imag();
-  }
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+      const size_t e = size_t(j) * n + i;
+      a_host[2 * e] = A(i, j).real();
+      a_host[2 * e + 1] = A(i, j).imag();
+      z_host[2 * e] = Z(i, j).real();
+      z_host[2 * e + 1] = Z(i, j).imag();
+    }
   for (int i = 0; i < n; ++i) {
     w_host[2 * i] = A(i, i).real();
     w_host[2 * i + 1] = A(i, i).imag();

@@ -58,7 +58,7 @@ def test_invalid_arguments_are_rejected_on_host():
     assert L.arnoldi_eigs(None, 5, 0.0, ctypes.byref(opts), None, None, None, None, None) == _lib.FQ_EINVAL
 
 
-@pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (7, 2), (40, 3), (120, 4)])
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (7, 2), (40, 3), (120, 4), (260, 5)])
 def test_host_schur_against_lapack(n, seed):
     from paper_2102_05054_amd import host_schur
     rng = np.random.default_rng(seed)
