@@ -151,15 +151,39 @@ __global__ void __launch_bounds__(1 << TB)
   const size_t voff = size_t(item >> a.tile_bits) * a.vstride;
   const C* __restrict__ xin = static_cast<const C*>(a.xin) + voff;
   C* __restrict__ xout = static_cast<C*>(a.xout) + voff;
-  for (int j = tid; j < N; j += T) lds[bw_phys(j)] = xin[tm.g(j)];
-  __syncthreads();
   const int ngroups = N >> WB;
-  for (int wi = 0; wi < a.nwin; ++wi) {
-    const WinU w = load_win(wins + wi);
-    const uint32_t below = (1u << w.b) - 1u;
+  // insert WB zero bits at position b: the first amplitude of window group g
+  auto group_base = [](uint32_t g, int b) {
+    return static_cast<int>((g & ((1u << b) - 1u)) | ((g >> b) << (b + WB)));
+  };
+  // The first window is applied on the way in and the last on the way out
+  // (one LDS write, resp. read, instead of a full round trip each) when
+  // every thread owns a window group and the window starts at tile bit 4 or
+  // higher, so that the groups of consecutive lanes are consecutive in the
+  // tile and the global accesses stay coalesced.
+  const bool own = ngroups >= T;
+  int first = 0, last = a.nwin;
+  if (own && a.nwin > 0 && load_win(wins).b >= 4) first = 1;
+  if (own && a.nwin > first && load_win(wins + a.nwin - 1).b >= 4) last = a.nwin - 1;
+  if (first == 1) {
+    const WinU w = load_win(wins);
     for (int g = tid; g < ngroups; g += T) {
-      // insert WB zero bits at position b
-      const int base = static_cast<int>((uint32_t(g) & below) | ((uint32_t(g) >> w.b) << (w.b + WB)));
+      const int base = group_base(uint32_t(g), w.b);
+      C v[1 << WB];
+#pragma unroll
+      for (int m = 0; m < (1 << WB); ++m) v[m] = xin[tm.g(base + (m << w.b))];
+      window_gates<Real, WB>(v, w, gates, mats);
+#pragma unroll
+      for (int m = 0; m < (1 << WB); ++m) lds[bw_phys(base + (m << w.b))] = v[m];
+    }
+  } else {
+    for (int j = tid; j < N; j += T) lds[bw_phys(j)] = xin[tm.g(j)];
+  }
+  __syncthreads();
+  for (int wi = first; wi < last; ++wi) {
+    const WinU w = load_win(wins + wi);
+    for (int g = tid; g < ngroups; g += T) {
+      const int base = group_base(uint32_t(g), w.b);
       C v[1 << WB];
 #pragma unroll
       for (int m = 0; m < (1 << WB); ++m) v[m] = lds[bw_phys(base + (m << w.b))];
@@ -172,12 +196,24 @@ __global__ void __launch_bounds__(1 << TB)
   const C rot = mk<Real>(static_cast<Real>(a.rot_re), static_cast<Real>(a.rot_im));
   const C pc = mk<Real>(static_cast<Real>(a.psi_coef_re), static_cast<Real>(a.psi_coef_im));
   const C* __restrict__ psi = static_cast<const C*>(a.psi) + voff;
-  for (int j = tid; j < N; j += T) {
-    const uint32_t g = tm.g(j);
-    C x = lds[bw_phys(j)];
+  auto finish = [&](C x, uint32_t g) {
     if (a.flags & BW_ROT) x = cmul(x, rot);
     if (a.flags & BW_ADD_PSI) x = (a.flags & BW_PSI_COEF) ? cfma(psi[g], pc, x) : cadd(x, psi[g]);
     xout[g] = x;
+  };
+  if (last < a.nwin) {
+    const WinU w = load_win(wins + last);
+    for (int g = tid; g < ngroups; g += T) {
+      const int base = group_base(uint32_t(g), w.b);
+      C v[1 << WB];
+#pragma unroll
+      for (int m = 0; m < (1 << WB); ++m) v[m] = lds[bw_phys(base + (m << w.b))];
+      window_gates<Real, WB>(v, w, gates, mats);
+#pragma unroll
+      for (int m = 0; m < (1 << WB); ++m) finish(v[m], tm.g(base + (m << w.b)));
+    }
+  } else {
+    for (int j = tid; j < N; j += T) finish(lds[bw_phys(j)], tm.g(j));
   }
 }
 
