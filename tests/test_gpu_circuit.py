@@ -92,3 +92,21 @@ def test_circuit_complex64_only_when_complex128_tiles_are_too_small():
         with pytest.raises(FloquetError):
             op.apply_U(to_dev(psi, torch.complex128))
     assert rel(out, models.circuit_apply(p, psi)) < TOL_U["c64"]
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("L,depth", [(14, 1), (14, 2), (16, 1), (17, 2)])
+def test_shallow_circuits_few_windows(dt, L, depth):
+    # shallow circuits give passes of one to three windows, so the first and
+    # last window fused with the tile's load and store coincide or touch
+    say(f"shallow circuit L={L} depth={depth} {dt}")
+    p = circuit(L, 870 + L + depth, depth=depth)
+    psi = random_state(2 ** L, 23, 3)
+    mv = lambda v: models.circuit_apply(p, v)  # noqa: E731
+    with circ_op(p) as op:
+        out_u = to_np(op.apply_U(to_dev(psi[0], _dt(dt))))
+        out_m = to_np(op.apply_filter_many(to_dev(psi, _dt(dt)), 5, 2.1))
+    assert rel(out_u, mv(psi[0])) < TOL_U[dt]
+    tol = 1e-12 * 6 if dt == "c128" else 2e-7 * 6 + 3e-6
+    for j in range(3):
+        assert rel(out_m[j], filters.geometric_sum(mv, psi[j], 5, 2.1)) < tol, j
