@@ -506,9 +506,27 @@ fq_status filter_many_ki(floquet_op* op, int k, double phi, int n, const void* p
   const cpx<Real>* thi = sizeof(Real) == 4 ? reinterpret_cast<const cpx<Real>*>(tab->thi32)
                                            : reinterpret_cast<const cpx<Real>*>(tab->thi64);
   const size_t d = op->dim();
-  const size_t need = size_t(n) * (sizeof(KiDesc<Real>) + sizeof(int));
-  const void* key[4] = {psi, out, tlo, thi};
-  bool same = op->many_n == n && std::equal(key, key + 4, op->many_key);
+  // descriptors: the problems (x = out_j), then two sets whose x is the
+  // kicked psi of tile group 0 / 1 (chi buffers), then the problem list.
+  // The folded passes are used for complex128 with 4 or more vectors: at
+  // L = 20 they take a 4-vector pass from 42.7 to 41.7 us but a 2-vector pass
+  // from 24.7 to 26.0 us, and the complex64 passes (phase entries prefetched)
+  // measured slower with them.
+  const bool kFold = sizeof(Real) == 8 && n >= 4;
+  const size_t need = size_t(n) * (3 * sizeof(KiDesc<Real>) + sizeof(int));
+  const size_t chi_need = kFold ? 2 * size_t(n) * d * sizeof(cpx<Real>) : 0;
+  bool fresh = false;
+  if (op->chi_cap < chi_need) {
+    (void)hipFree(op->chi_mem);  // waits for work still reading it
+    op->chi_mem = nullptr;
+    op->chi_cap = 0;
+    FQ_HIP_CHECK(hipMalloc(&op->chi_mem, chi_need));
+    op->chi_cap = chi_need;
+    fresh = true;
+  }
+  cpx<Real>* chi = kFold ? static_cast<cpx<Real>*>(op->chi_mem) : nullptr;
+  const void* key[5] = {psi, out, tlo, thi, chi};
+  bool same = !fresh && op->many_n == n && std::equal(key, key + 5, op->many_key);
   if (op->many_cap < need) {
     (void)hipFree(op->many_mem);  // waits for work still reading it
     op->many_mem = nullptr;
@@ -518,24 +536,30 @@ fq_status filter_many_ki(floquet_op* op, int k, double phi, int n, const void* p
     same = false;
   }
   KiDesc<Real>* desc = static_cast<KiDesc<Real>*>(op->many_mem);
-  int* list = reinterpret_cast<int*>(desc + n);
+  int* list = reinterpret_cast<int*>(desc + 3 * size_t(n));
   if (!same) {
     std::vector<unsigned char> h(need);
     KiDesc<Real>* hd = reinterpret_cast<KiDesc<Real>*>(h.data());
-    int* hl = reinterpret_cast<int*>(hd + n);
+    int* hl = reinterpret_cast<int*>(hd + 3 * size_t(n));
     for (int j = 0; j < n; ++j) {
-      hd[j] = KiDesc<Real>{static_cast<const cpx<Real>*>(psi) + size_t(j) * d,
-                           static_cast<cpx<Real>*>(out) + size_t(j) * d, tlo, thi, op->w, 0.0};
+      const cpx<Real>* pj = static_cast<const cpx<Real>*>(psi) + size_t(j) * d;
+      cpx<Real>* c0 = kFold ? chi + size_t(j) * d : nullptr;
+      cpx<Real>* c1 = kFold ? chi + (size_t(n) + j) * d : nullptr;
+      hd[j] = KiDesc<Real>{pj, static_cast<cpx<Real>*>(out) + size_t(j) * d, tlo, thi, op->w, 0.0, {c0, c1}};
+      hd[n + j] = KiDesc<Real>{pj, c0, tlo, thi, op->w, 0.0, {nullptr, nullptr}};
+      hd[2 * n + j] = KiDesc<Real>{pj, c1, tlo, thi, op->w, 0.0, {nullptr, nullptr}};
       hl[j] = j;
     }
     FQ_HIP_CHECK(hipMemcpyAsync(desc, h.data(), need, hipMemcpyHostToDevice, s));
     FQ_HIP_CHECK(hipStreamSynchronize(s));  // h is pageable and local
-    std::copy(key, key + 4, op->many_key);
+    std::copy(key, key + 5, op->many_key);
     op->many_n = n;
   }
+  const KiDesc<Real>* chi0 = kFold ? desc + n : nullptr;
+  const KiDesc<Real>* chi1 = kFold ? desc + 2 * size_t(n) : nullptr;
   KiBatchShape sh;
-  FQ_TRY(ki_batch_tune<Real>(op->L, op->sw, k, desc, list, static_cast<unsigned>(n), s, &sh, nullptr));
-  return ki_batch_filter<Real>(sh, k, desc, list, static_cast<unsigned>(n), s);
+  FQ_TRY(ki_batch_tune<Real>(op->L, op->sw, k, desc, list, static_cast<unsigned>(n), s, &sh, nullptr, chi0, chi1));
+  return ki_batch_filter<Real>(sh, k, desc, list, static_cast<unsigned>(n), s, chi0, chi1);
 }
 
 }  // namespace

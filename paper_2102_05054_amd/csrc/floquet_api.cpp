@@ -611,6 +611,7 @@ fq_status destroy_floquet_op(floquet_op* op) {
   (void)hipFree(op->out32);
   (void)hipFree(op->coefs_dev);
   (void)hipFree(op->many_mem);
+  (void)hipFree(op->chi_mem);
   (void)hipFree(op->V);
   (void)hipFree(op->work);
   (void)hipFree(op->work2);

@@ -58,7 +58,7 @@ fq_status launch_err(const char* what, hipError_t e) {
 
 template <typename Real>
 fq_status bpass(const KiBatchShape& sh, const KiGroup& g, const KiDesc<Real>* desc, const int* list, unsigned n,
-                int from_psi, int flags, bool k2, hipStream_t s) {
+                int from_psi, int flags, bool k2, hipStream_t s, int chi = 0) {
   KiPassArgs<Real> a{};
   a.n = g.n;
   a.c = g.c;
@@ -72,13 +72,15 @@ fq_status bpass(const KiBatchShape& sh, const KiGroup& g, const KiDesc<Real>* de
     a.flags |= KI_PREFETCH_PHASE;
   a.k1 = masks_for(g.kbits, g.n, g.rb, g.tb);
   a.k2 = k2 ? a.k1 : KickMasks{0, 0, 0, 0};
+  a.chi = chi;
   a.desc = desc;
   a.list = list;
   a.from_psi = from_psi;
   a.flat = sh.flat ? 1 : 0;
   a.tile_log = 0;
   while ((1u << a.tile_log) < g.ntiles) ++a.tile_log;
-  if (sh.pipe > 0 && pipe_shape(g.rb, g.tb, sizeof(Real) == 4)) {
+  // the pipelined form has no folded variant
+  if (sh.pipe > 0 && chi == 0 && pipe_shape(g.rb, g.tb, sizeof(Real) == 4)) {
     const size_t items = size_t(g.ntiles) * n;
     const unsigned grid = static_cast<unsigned>(std::min<size_t>(sh.pipe, (items / 2) & ~size_t(7)));
     if (grid >= 8 && (g.ntiles & 7u) == 0u) {
@@ -165,7 +167,7 @@ std::vector<KiBatchShape> ki_batch_candidates(int L, bool sw, bool c64_dt) {
 
 template <typename Real>
 fq_status ki_batch_filter(const KiBatchShape& sh, int k, const KiDesc<Real>* desc, const int* list, unsigned n,
-                          hipStream_t s) {
+                          hipStream_t s, const KiDesc<Real>* chi0, const KiDesc<Real>* chi1) {
   if (n == 0) return FQ_OK;
   if (k < 1) {
     set_error("internal: batched filter needs k >= 1");
@@ -176,7 +178,7 @@ fq_status ki_batch_filter(const KiBatchShape& sh, int k, const KiDesc<Real>* des
     KiBatchShape one = sh;
     one.chunk = 0;
     for (unsigned c0 = 0; c0 < n; c0 += sh.chunk) {
-      const fq_status st = ki_batch_filter<Real>(one, k, desc, list + c0, std::min(sh.chunk, n - c0), s);
+      const fq_status st = ki_batch_filter<Real>(one, k, desc, list + c0, std::min(sh.chunk, n - c0), s, chi0, chi1);
       if (st != FQ_OK) return st;
     }
     return FQ_OK;
@@ -188,11 +190,21 @@ fq_status ki_batch_filter(const KiBatchShape& sh, int k, const KiDesc<Real>* des
   }
   fq_status st;
   if (pl.ngroups == 2) {
+    const bool fold = chi0 && chi1 && k >= 2;
+    if (fold) {
+      // chi_g = K_g psi for both groups
+      st = bpass<Real>(sh, pl.grp[0], chi0, list, n, 1, 0, false, s);
+      if (st != FQ_OK) return st;
+      st = bpass<Real>(sh, pl.grp[1], chi1, list, n, 1, 0, false, s);
+      if (st != FQ_OK) return st;
+    }
     // prologue: kick of the second group on psi; then alternate the groups
     st = bpass<Real>(sh, pl.grp[1], desc, list, n, 1, 0, false, s);
     if (st != FQ_OK) return st;
     for (int step = 1; step <= k; ++step) {
-      st = bpass<Real>(sh, pl.grp[(step - 1) & 1], desc, list, n, 0, KI_PHASE | KI_ADD_PSI, step < k, s);
+      const int g = (step - 1) & 1;
+      st = bpass<Real>(sh, pl.grp[g], desc, list, n, 0, KI_PHASE | KI_ADD_PSI, step < k, s,
+                       fold && step < k ? g + 1 : 0);
       if (st != FQ_OK) return st;
     }
     return FQ_OK;
@@ -260,7 +272,8 @@ fq_status ki_set_policy(int policy) {
 
 template <typename Real>
 fq_status ki_batch_tune(int L, bool sw, int k, const KiDesc<Real>* desc, const int* list, unsigned n,
-                        hipStream_t s, KiBatchShape* out, double* best_us) {
+                        hipStream_t s, KiBatchShape* out, double* best_us, const KiDesc<Real>* chi0,
+                        const KiDesc<Real>* chi1) {
   const bool c64_dt = sizeof(Real) == 4;
   const auto key = std::make_tuple(L, sw, c64_dt, k, size_class(n));
   int policy;
@@ -285,13 +298,13 @@ fq_status ki_batch_tune(int L, bool sw, int k, const KiDesc<Real>* desc, const i
   FQ_HIP_CHECK(hipEventCreate(&e1));
   // time per Horner step of one candidate (negative: could not be launched)
   auto time_one = [&](const KiBatchShape& c) -> double {
-    if (ki_batch_filter<Real>(c, kt, desc, list, n, s) != FQ_OK) {
+    if (ki_batch_filter<Real>(c, kt, desc, list, n, s, chi0, chi1) != FQ_OK) {
       (void)hipGetLastError();
       return -1.0;
     }
     (void)hipEventRecord(e0, s);
     bool ok = true;
-    for (int r = 0; r < 2 && ok; ++r) ok = ki_batch_filter<Real>(c, kt, desc, list, n, s) == FQ_OK;
+    for (int r = 0; r < 2 && ok; ++r) ok = ki_batch_filter<Real>(c, kt, desc, list, n, s, chi0, chi1) == FQ_OK;
     (void)hipEventRecord(e1, s);
     if (hipEventSynchronize(e1) != hipSuccess || !ok) {
       (void)hipGetLastError();
@@ -362,16 +375,16 @@ fq_status ki_batch_tune(int L, bool sw, int k, const KiDesc<Real>* desc, const i
 }
 
 template fq_status ki_batch_filter<float>(const KiBatchShape&, int, const KiDesc<float>*, const int*, unsigned,
-                                          hipStream_t);
+                                          hipStream_t, const KiDesc<float>*, const KiDesc<float>*);
 template fq_status ki_batch_filter<double>(const KiBatchShape&, int, const KiDesc<double>*, const int*, unsigned,
-                                           hipStream_t);
+                                           hipStream_t, const KiDesc<double>*, const KiDesc<double>*);
 template fq_status ki_batch_apply<float>(const KiBatchShape&, const KiDesc<float>*, const int*, unsigned,
                                          hipStream_t);
 template fq_status ki_batch_apply<double>(const KiBatchShape&, const KiDesc<double>*, const int*, unsigned,
                                           hipStream_t);
 template fq_status ki_batch_tune<float>(int, bool, int, const KiDesc<float>*, const int*, unsigned, hipStream_t,
-                                        KiBatchShape*, double*);
+                                        KiBatchShape*, double*, const KiDesc<float>*, const KiDesc<float>*);
 template fq_status ki_batch_tune<double>(int, bool, int, const KiDesc<double>*, const int*, unsigned, hipStream_t,
-                                         KiBatchShape*, double*);
+                                         KiBatchShape*, double*, const KiDesc<double>*, const KiDesc<double>*);
 
 }  // namespace fq

@@ -37,9 +37,13 @@ std::vector<KiBatchShape> ki_batch_candidates(int L, bool sw, bool c64_dt);
 
 // x_q = g_k(U_q) psi_q for the problems desc[list[0..n)] (geometric sum; the
 // rotation e^{-i phi_q} and the kick scales live in each problem's tables).
+// With chi0 / chi1 (descriptors whose x is the problem's desc.chi[0] /
+// desc.chi[1] buffer, same indexing as desc) two-group plans first write
+// chi_g = K_g psi and then run every Horner pass but the last in the folded
+// form (KiPassArgs::chi).
 template <typename Real>
 fq_status ki_batch_filter(const KiBatchShape& sh, int k, const KiDesc<Real>* desc, const int* list, unsigned n,
-                          hipStream_t s);
+                          hipStream_t s, const KiDesc<Real>* chi0 = nullptr, const KiDesc<Real>* chi1 = nullptr);
 
 // x_q = U_q psi_q.
 template <typename Real>
@@ -57,6 +61,7 @@ fq_status ki_set_policy(int policy);
 // class).  best_us (optional) receives the time per Horner step of the batch.
 template <typename Real>
 fq_status ki_batch_tune(int L, bool sw, int k, const KiDesc<Real>* desc, const int* list, unsigned n,
-                        hipStream_t s, KiBatchShape* out, double* best_us);
+                        hipStream_t s, KiBatchShape* out, double* best_us, const KiDesc<Real>* chi0 = nullptr,
+                        const KiDesc<Real>* chi1 = nullptr);
 
 }  // namespace fq

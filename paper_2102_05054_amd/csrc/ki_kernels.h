@@ -30,6 +30,10 @@ struct KiDesc {
   const cpx<Real>* thi;
   double w;
   double pad;
+  // chi[g] = K_g psi, the kick of tile group g applied to psi (or null): a
+  // pass that ends with the kick of its own group then adds chi[g] instead
+  // of kicking psi (KiPassArgs::chi)
+  const cpx<Real>* chi[2];
 };
 
 template <typename Real>
@@ -54,6 +58,12 @@ struct KiPassArgs {
   const int* list;
   int from_psi;
   int flat, tile_log;
+  // batched passes with k2 == k1 (kick, phase, +psi, the same kick again):
+  // chi = g + 1 computes K D K x + chi[g] with chi[g] = K psi from the
+  // problem's descriptor.  The kicks commute, so the layout-B parts of both
+  // kicks and the phase run between one A->B and one B->A change (two
+  // layout changes per pass instead of four).  0: plain psi.
+  int chi;
 };
 
 template <typename Real>

@@ -120,7 +120,10 @@ __device__ __forceinline__ cpx<Real> ki_phase(const cpx<Real>* __restrict__ tlo,
 // ---------------------------------------------------------------------------
 // One pass over all tiles of one group (see ki_kernels.h for the fields).
 // ---------------------------------------------------------------------------
-template <typename Real, int RB, int TB, bool SW, bool PF, bool BATCH>
+// BATCH: 0 one problem, 1 batched, 2 batched with the folded form
+// (KiPassArgs::chi; a kernel of its own, as its extra registers would lower
+// the occupancy of the plain form)
+template <typename Real, int RB, int TB, bool SW, bool PF, int BATCH>
 __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
   using C = cpx<Real>;
   constexpr int R = 1 << RB;
@@ -134,7 +137,7 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
   const C* __restrict__ tlo;
   const C* __restrict__ thi;
   Real w;
-  if constexpr (BATCH) {
+  if constexpr (BATCH != 0) {
     uint32_t q;
     if (a.flat) {
       const uint32_t idx = xcd_tile(blockIdx.x, gridDim.x);
@@ -147,7 +150,7 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
     const KiDesc<Real>& D = a.desc[a.list[q]];
     xin = a.from_psi ? D.psi : D.x;
     xout = D.x;
-    psi = D.psi;
+    psi = (BATCH == 2 && a.chi > 0) ? D.chi[a.chi - 1] : D.psi;
     tlo = D.tlo;
     thi = D.thi;
     w = static_cast<Real>(D.w);
@@ -163,6 +166,12 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
   const TileMap tm = make_tile_map(tile, a.n, a.c, a.p);
   const bool do_ph = (a.flags & KI_PHASE) != 0;
   const bool do_ps = (a.flags & KI_ADD_PSI) != 0;
+  // folded form (KiPassArgs::chi): the phase is applied in layout B
+  bool fold = false, fold_b = false;
+  if constexpr (BATCH == 2) {
+    fold = a.chi > 0;
+    fold_b = fold && ((a.k1.regB | a.k1.laneB | a.k2.regB | a.k2.laneB) != 0u);
+  }
 
   // The tile and psi are read in layout A (consecutive lanes <-> consecutive
   // addresses) at the start; the phase and +psi are applied in layout A too,
@@ -180,7 +189,7 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
   if constexpr (PF) {
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-      const uint32_t g = tm.g(tid + (m << TB));
+      const uint32_t g = tm.g(fold_b ? (tid << RB) + m : tid + (m << TB));
       tl[m] = gload(tlo, g & ((1u << a.m) - 1u));
       th[m] = gload(thi, ((g >> a.m) << 2) | ((g & 1u) << 1) | ((g >> (a.m - 1)) & 1u));
     }
@@ -189,6 +198,37 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
     const C s = mk<Real>(static_cast<Real>(a.in_coef_re), static_cast<Real>(a.in_coef_im));
 #pragma unroll
     for (int m = 0; m < R; ++m) v[m] = cmul(v[m], s);
+  }
+
+  if (fold) {
+    // K D K x + chi: the A part of the first kick, then in layout B its B
+    // part, the phase and the B part of the second kick, back in A the A
+    // part of the second kick and chi (read in layout A)
+    kick_regs<Real, RB, SW>(v, a.k1.regA, w);
+    kick_lanes<Real, RB, SW>(v, a.k1.laneA, w);
+    if (fold_b) a_to_b<Real, RB, TB>(v, lds, tid);
+    kick_regs<Real, RB, SW>(v, a.k1.regB, w);
+    kick_lanes<Real, RB, SW>(v, a.k1.laneB, w);
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const int t = fold_b ? (tid << RB) + m : tid + (m << TB);
+      if constexpr (pre_ph)
+        v[m] = cmul(v[m], cmul(tl[m], th[m]));
+      else
+        v[m] = cmul(v[m], ki_phase(tlo, thi, tm.g(t), a.m));
+    }
+    kick_regs<Real, RB, SW>(v, a.k2.regB, w);
+    kick_lanes<Real, RB, SW>(v, a.k2.laneB, w);
+    if (fold_b) b_to_a<Real, RB, TB>(v, lds, tid);
+    kick_regs<Real, RB, SW>(v, a.k2.regA, w);
+    kick_lanes<Real, RB, SW>(v, a.k2.laneA, w);
+    const C pc = mk<Real>(static_cast<Real>(a.psi_coef_re), static_cast<Real>(a.psi_coef_im));
+    const bool coef = (a.flags & KI_PSI_COEF) != 0;
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = coef ? cfma(ps[m], pc, v[m]) : cadd(v[m], ps[m]);
+#pragma unroll
+    for (int m = 0; m < R; ++m) gstore(xout, tm.g(tid + (m << TB)), v[m]);
+    return;
   }
 
   // first kick of this group: layout A, then layout B, back to A.  A thread
@@ -481,7 +521,7 @@ __global__ void __launch_bounds__(1 << TB) ki_single_kernel(KiSingleArgs<Real> a
 // ---------------------------------------------------------------------------
 namespace {
 
-template <typename Real, int RB, int TB, bool SW, bool PF, bool BATCH>
+template <typename Real, int RB, int TB, bool SW, bool PF, int BATCH>
 hipError_t launch_pass_t(const KiPassArgs<Real>& a, unsigned ntiles, unsigned nprob, hipStream_t s) {
   const size_t shmem = static_cast<size_t>(lds_slots<RB, TB>()) * sizeof(cpx<Real>);
   auto kern = ki_pass_kernel<Real, RB, TB, SW, PF, BATCH>;
@@ -492,7 +532,7 @@ hipError_t launch_pass_t(const KiPassArgs<Real>& a, unsigned ntiles, unsigned np
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  const dim3 grid = !BATCH ? dim3(ntiles) : (a.flat ? dim3(ntiles * nprob) : dim3(ntiles, nprob));
+  const dim3 grid = BATCH == 0 ? dim3(ntiles) : (a.flat ? dim3(ntiles * nprob) : dim3(ntiles, nprob));
   hipLaunchKernelGGL(kern, grid, dim3(1 << TB), shmem, s, a);
   return hipGetLastError();
 }
@@ -546,14 +586,22 @@ hipError_t ki_launch_pass(const KiPassArgs<Real>& a, int rb, int tb, bool sw, un
                           unsigned nprob) {
   const bool pf = (a.flags & KI_PREFETCH_PHASE) != 0;
   if (nprob > 0 && (!a.desc || !a.list || nprob > 65535u)) return hipErrorInvalidValue;
+  // the folded form exists for complex128 batched passes only
+  if (a.chi > 0 && (nprob == 0 || sizeof(Real) != 8)) return hipErrorInvalidValue;
   if (nprob > 0 && a.flat && (ntiles != (1u << a.tile_log) || size_t(ntiles) * nprob > 0x7fffffffu))
     return hipErrorInvalidValue;
 #define FQ_CASE4(RB_, TB_, PF_)                                                                    \
-  if (nprob > 0)                                                                                   \
-    return sw ? launch_pass_t<Real, RB_, TB_, true, PF_, true>(a, ntiles, nprob, s)                \
-              : launch_pass_t<Real, RB_, TB_, false, PF_, true>(a, ntiles, nprob, s);              \
-  return sw ? launch_pass_t<Real, RB_, TB_, true, PF_, false>(a, ntiles, 1, s)                     \
-            : launch_pass_t<Real, RB_, TB_, false, PF_, false>(a, ntiles, 1, s);
+  if (nprob > 0) {                                                                                 \
+    if constexpr (sizeof(Real) == 8) {                                                             \
+      if (a.chi > 0)                                                                               \
+        return sw ? launch_pass_t<Real, RB_, TB_, true, PF_, 2>(a, ntiles, nprob, s)               \
+                  : launch_pass_t<Real, RB_, TB_, false, PF_, 2>(a, ntiles, nprob, s);             \
+    }                                                                                              \
+    return sw ? launch_pass_t<Real, RB_, TB_, true, PF_, 1>(a, ntiles, nprob, s)                   \
+              : launch_pass_t<Real, RB_, TB_, false, PF_, 1>(a, ntiles, nprob, s);                 \
+  }                                                                                                \
+  return sw ? launch_pass_t<Real, RB_, TB_, true, PF_, 0>(a, ntiles, 1, s)                         \
+            : launch_pass_t<Real, RB_, TB_, false, PF_, 0>(a, ntiles, 1, s);
 #define FQ_CASE(RB_, TB_)                                                                          \
   if (rb == RB_ && tb == TB_) {                                                                    \
     if (pf) {                                                                                      \

@@ -85,8 +85,11 @@ struct floquet_op {
   // (re-uploaded only when the vectors, count, precision or tables change)
   void* many_mem = nullptr;
   size_t many_cap = 0;
-  const void* many_key[4] = {nullptr, nullptr, nullptr, nullptr};
+  const void* many_key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   int many_n = 0;
+  // ... and the kicked psi of each tile group (2 x n states) for its folded passes
+  void* chi_mem = nullptr;
+  size_t chi_cap = 0;
 
   // Krylov workspace (complex128): V (d x ncv_cap+1) and helpers
   void* V = nullptr;
