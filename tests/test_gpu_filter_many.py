@@ -129,3 +129,22 @@ def test_filter_many_circuit(dt):
     for j in range(n):
         ref = filters.geometric_sum(lambda v: models.circuit_apply(p, v), psi[j], k, 0.6)
         assert rel(out[j], ref) < _tol(dt, k), j
+
+
+def test_filter_many_folded_passes_match_single_vector_filter():
+    # four complex128 vectors per launch take the folded passes (K D K x + K psi
+    # with K psi precomputed per tile group); the single-vector filter does
+    # not: both agree to rounding, and vector 0 matches the oracle
+    torch = require_gpu()
+    L, n, k, phi = 20, 4, 6, 0.45
+    say(f"apply_filter_many folded L={L} n={n} k={k}")
+    p = kicked_ising(L, 760)
+    psi = random_state(2 ** L, 61, n)
+    with ki_op(p) as op:
+        dpsi = to_dev(psi, torch.complex128)
+        many = to_np(op.apply_filter_many(dpsi, k, phi))
+        ones = [to_np(op.apply_filter(dpsi[j], k, phi)) for j in range(n)]
+    for j in range(n):
+        assert rel(many[j], ones[j]) < 1e-13, j
+    ref = filters.geometric_sum(lambda v: models.ki_apply(p, v), psi[0], k, phi)
+    assert rel(many[0], ref) < _tol("c128", k)
