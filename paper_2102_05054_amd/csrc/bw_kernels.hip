@@ -158,13 +158,14 @@ __global__ void __launch_bounds__(1 << TB)
   };
   // The first window is applied on the way in and the last on the way out
   // (one LDS write, resp. read, instead of a full round trip each) when
-  // every thread owns a window group and the window starts at tile bit 4 or
-  // higher, so that the groups of consecutive lanes are consecutive in the
-  // tile and the global accesses stay coalesced.
+  // every thread owns a window group.  For a window at low tile bits the
+  // lanes then touch strided 16-byte pieces, but consecutive accesses of a
+  // thread fill the same lines: fusing at any position measured 1-3 %
+  // faster than only for windows at tile bit 4 and up (L = 16..20).
   const bool own = ngroups >= T;
   int first = 0, last = a.nwin;
-  if (own && a.nwin > 0 && load_win(wins).b >= 4) first = 1;
-  if (own && a.nwin > first && load_win(wins + a.nwin - 1).b >= 4) last = a.nwin - 1;
+  if (own && a.nwin > 0) first = 1;
+  if (own && a.nwin > first) last = a.nwin - 1;
   if (first == 1) {
     const WinU w = load_win(wins);
     for (int g = tid; g < ngroups; g += T) {
