@@ -512,9 +512,9 @@ fq_status filter_many_ki(floquet_op* op, int k, double phi, int n, const void* p
   // L = 20 they take a 4-vector pass from 42.7 to 41.7 us but a 2-vector pass
   // from 24.7 to 26.0 us, and the complex64 passes (phase entries prefetched)
   // measured slower with them.
-  const bool kFold = sizeof(Real) == 8 && n >= 4;
+  const bool fold = sizeof(Real) == 8 && n >= 4;
   const size_t need = size_t(n) * (3 * sizeof(KiDesc<Real>) + sizeof(int));
-  const size_t chi_need = kFold ? 2 * size_t(n) * d * sizeof(cpx<Real>) : 0;
+  const size_t chi_need = fold ? 2 * size_t(n) * d * sizeof(cpx<Real>) : 0;
   bool fresh = false;
   if (op->chi_cap < chi_need) {
     (void)hipFree(op->chi_mem);  // waits for work still reading it
@@ -524,7 +524,7 @@ fq_status filter_many_ki(floquet_op* op, int k, double phi, int n, const void* p
     op->chi_cap = chi_need;
     fresh = true;
   }
-  cpx<Real>* chi = kFold ? static_cast<cpx<Real>*>(op->chi_mem) : nullptr;
+  cpx<Real>* chi = fold ? static_cast<cpx<Real>*>(op->chi_mem) : nullptr;
   const void* key[5] = {psi, out, tlo, thi, chi};
   bool same = !fresh && op->many_n == n && std::equal(key, key + 5, op->many_key);
   if (op->many_cap < need) {
@@ -543,8 +543,8 @@ fq_status filter_many_ki(floquet_op* op, int k, double phi, int n, const void* p
     int* hl = reinterpret_cast<int*>(hd + 3 * size_t(n));
     for (int j = 0; j < n; ++j) {
       const cpx<Real>* pj = static_cast<const cpx<Real>*>(psi) + size_t(j) * d;
-      cpx<Real>* c0 = kFold ? chi + size_t(j) * d : nullptr;
-      cpx<Real>* c1 = kFold ? chi + (size_t(n) + j) * d : nullptr;
+      cpx<Real>* c0 = fold ? chi + size_t(j) * d : nullptr;
+      cpx<Real>* c1 = fold ? chi + (size_t(n) + j) * d : nullptr;
       hd[j] = KiDesc<Real>{pj, static_cast<cpx<Real>*>(out) + size_t(j) * d, tlo, thi, op->w, 0.0, {c0, c1}};
       hd[n + j] = KiDesc<Real>{pj, c0, tlo, thi, op->w, 0.0, {nullptr, nullptr}};
       hd[2 * n + j] = KiDesc<Real>{pj, c1, tlo, thi, op->w, 0.0, {nullptr, nullptr}};
@@ -555,8 +555,8 @@ fq_status filter_many_ki(floquet_op* op, int k, double phi, int n, const void* p
     std::copy(key, key + 5, op->many_key);
     op->many_n = n;
   }
-  const KiDesc<Real>* chi0 = kFold ? desc + n : nullptr;
-  const KiDesc<Real>* chi1 = kFold ? desc + 2 * size_t(n) : nullptr;
+  const KiDesc<Real>* chi0 = fold ? desc + n : nullptr;
+  const KiDesc<Real>* chi1 = fold ? desc + 2 * size_t(n) : nullptr;
   KiBatchShape sh;
   FQ_TRY(ki_batch_tune<Real>(op->L, op->sw, k, desc, list, static_cast<unsigned>(n), s, &sh, nullptr, chi0, chi1));
   return ki_batch_filter<Real>(sh, k, desc, list, static_cast<unsigned>(n), s, chi0, chi1);
