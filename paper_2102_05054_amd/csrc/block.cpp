@@ -508,11 +508,12 @@ fq_status filter_many_ki(floquet_op* op, int k, double phi, int n, const void* p
   const size_t d = op->dim();
   // descriptors: the problems (x = out_j), then two sets whose x is the
   // kicked psi of tile group 0 / 1 (chi buffers), then the problem list.
-  // The folded passes are used for complex128 with 4 or more vectors: at
-  // L = 20 they take a 4-vector pass from 42.7 to 41.7 us but a 2-vector pass
-  // from 24.7 to 26.0 us, and the complex64 passes (phase entries prefetched)
-  // measured slower with them.
-  const bool fold = sizeof(Real) == 8 && n >= 4;
+  // The folded passes are used for complex128 with 4 vectors: at L = 20 they
+  // take a 4-vector pass from 42.7 to 41.7 us, but a 2-vector pass from 24.7
+  // to 26.0 us and an 8-vector pass from 77.5 to 84.3 us (the folded kernel
+  // keeps one wave per SIMD less resident), and the complex64 passes (phase
+  // entries prefetched) measured slower with them.
+  const bool fold = sizeof(Real) == 8 && n == 4;
   const size_t need = size_t(n) * (3 * sizeof(KiDesc<Real>) + sizeof(int));
   const size_t chi_need = fold ? 2 * size_t(n) * d * sizeof(cpx<Real>) : 0;
   bool fresh = false;
