@@ -38,6 +38,8 @@ import resource
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -61,9 +63,12 @@ def parse():
     ap.add_argument("--no-c128", action="store_true", help="skip the complex128 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--roofline-steps", type=int, default=2000)
+    ap.add_argument("--budget", type=float, default=400.0,
+                    help="wall-clock budget in seconds of the default run: timed solves stop early so that the "
+                         "comparison solve, the roofline passes and the JSON line fit in it")
     ap.add_argument("--scan-L", type=int, default=None,
                     help="(n_cv, k) scan of the brickwork circuit at this L (n_ev=50, z=1, complex128)")
-    ap.add_argument("--workload", default="ki_L20", choices=["ki_L20", "ki_batched", "bw_L24", "bw_paper"],
+    ap.add_argument("--workload", default="ki_L20", choices=["ki_L20", "ki_batched", "bw_L24", "bw_paper", "nominal"],
                     help="ki_batched: 256 realisations x 4 targets, L in 12..16, one batched call; "
                          "bw_L24: the brickwork filter (k=300) at L=24")
     ap.add_argument("--filter-steps", type=int, default=0,
@@ -167,23 +172,30 @@ def profile_gemm(op, L, ncv, nev, block):
                       "rotation_flop": 8 * d * m * p, "rotation_bytes": 16 * d * (m + p)}))
 
 
-def traffic_file(nvec):
-    name = "ki_pass_kernel_L20_traffic.json" if nvec == 1 else f"ki_pass_kernel_L20_block{nvec}_traffic.json"
+def traffic_file(nvec, L=20):
+    if L == 20:
+        name = "ki_pass_kernel_L20_traffic.json" if nvec == 1 else f"ki_pass_kernel_L20_block{nvec}_traffic.json"
+    else:
+        name = f"ki_pass_kernel_L{L}_traffic.json"
     return os.path.join(ROOT, "profiles", name)
 
 
-def traffic_per_pass(nvec, dtype):
+def traffic_per_pass(nvec, dtype, L=20):
     """Calibrated HBM bytes per pass launch (nvec vectors) from the committed
     counter summary, only when it was measured on the current kernel source."""
     try:
         from paper_2102_05054_amd.traffic import kernel_hash
-        with open(traffic_file(nvec)) as f:
+        with open(traffic_file(nvec, L)) as f:
             rec = json.load(f)
         if rec.get("kernel_hash") == kernel_hash():
             return rec.get(f"bytes_per_pass_{dtype}", rec["bytes_per_pass"] if dtype == "c64" else None)
     except (OSError, ValueError, KeyError):
         pass
     return None
+
+
+def traffic_per_pass_L24(dtype):
+    return traffic_per_pass(1, dtype, L=24)
 
 
 def scan(L, nev=50):
@@ -480,18 +492,18 @@ def brickwork_block_filter(args, op, L):
     }))
 
 
-def cpu_baseline(p, seconds=15.0):
-    """The oracle's matrix-free U (complex128 NumPy) on the host: U-apps/s on a
-    bounded sample of the same state size."""
-    import numpy as np
-
+def _cpu_worker(L, J, h, g, periodic, seconds, seed):
+    """One host process: the oracle's matrix-free complex128 U applied
+    repeatedly for about ``seconds``; returns (applications, wall, CPU time)."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
     from oracle import models
-    from workloads import start_vector
-    psi = start_vector(2 ** p.L, 3000)
+    from workloads import KickedIsingParams, start_vector
+    import numpy as np
+    p = KickedIsingParams(L=L, J=np.asarray(J), h=np.asarray(h), g=g, periodic=periodic, phi=0.0)
+    x = start_vector(2 ** L, seed)
     ru0 = resource.getrusage(resource.RUSAGE_SELF)
     t0 = time.perf_counter()
     n = 0
-    x = psi
     while True:
         x = models.ki_apply(p, x)
         n += 1
@@ -499,12 +511,60 @@ def cpu_baseline(p, seconds=15.0):
             break
     wall = time.perf_counter() - t0
     ru1 = resource.getrusage(resource.RUSAGE_SELF)
-    cpu = (ru1.ru_utime - ru0.ru_utime) + (ru1.ru_stime - ru0.ru_stime)
+    return n, wall, (ru1.ru_utime - ru0.ru_utime) + (ru1.ru_stime - ru0.ru_stime)
+
+
+def host_cores():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    # the GPU machine gives one GPU a 16-CPU share, whatever the machine shows
+    return max(1, min(n, 16))
+
+
+def cpu_baseline(p, seconds=12.0):
+    """The oracle's matrix-free U (complex128 NumPy, single-threaded as
+    written) on every host core: one process per core, each applying U to
+    its own state for a bounded time.  Runs before the GPU is initialised."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    workers = host_cores()
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        futs = [ex.submit(_cpu_worker, p.L, list(map(float, p.J)), list(map(float, p.h)), float(p.g),
+                          bool(p.periodic), seconds, 3000 + i) for i in range(workers)]
+        res = [f.result() for f in futs]
+    wall_all = time.perf_counter() - t0
+    n = sum(r[0] for r in res)
+    rate = sum(r[0] / r[1] for r in res)
+    cpu = sum(r[2] for r in res)
+    busy = max(r[1] for r in res)
     return {
-        "value": n / wall, "unit": "U-applications/s", "cores": round(cpu / wall, 2), "kind": "oracle",
-        "sample": f"{n} matrix-free complex128 U applications of the oracle at L={p.L} "
-                  f"({wall:.1f} s wall, {cpu:.1f} s CPU, host has {os.cpu_count()} logical CPUs)",
+        "value": rate, "unit": "U-applications/s", "cores": round(cpu / busy, 2), "kind": "oracle",
+        "sample": f"{n} matrix-free complex128 U applications of the oracle at L={p.L}, {workers} host processes "
+                  f"x ~{seconds:.0f} s each ({wall_all:.1f} s wall with start-up, {cpu:.1f} s CPU; the host shows "
+                  f"{os.cpu_count()} logical CPUs, of which {workers} were used)",
     }
+
+
+def pass_roofline_L24(seconds_cap=20.0):
+    """The kicked-Ising Horner pass at L = 24 (d = 16,777,216), where w and psi
+    (2 x 128 MiB complex64, 2 x 256 MiB complex128) exceed the 256 MB
+    Infinity Cache, one vector per launch: average pass duration from HIP
+    events on the launch stream, 3 * d * s algorithmic bytes per pass."""
+    from paper_2102_05054_amd import kicked_ising
+    from workloads import config_kicked_ising
+    q = config_kicked_ising("ki_L20", W=1.0, L=24)
+    out = {}
+    with kicked_ising(q.L, q.J, q.h, q.g, q.periodic) as op24:
+        for dt in ("c64", "c128"):
+            r = filter_roofline(op24, 24, 200, 1, dt)
+            out[dt] = {"kernel": r["kernel"], "avg_launch_us": r["avg_launch_us"],
+                       "bytes_per_launch": r["bytes_per_launch"], "achieved": r["achieved_GBs"],
+                       "peak": 8000.0, "unit": "GB/s", "frac": r["achieved_GBs"] / 8000.0,
+                       "traffic": traffic_per_pass_L24(dt)}
+    return out
 
 
 def main():
@@ -512,12 +572,7 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1 (multi-GPU sharding is a design note only)"}))
         sys.exit(2)
-    import numpy as np
-    import torch
-
-    from paper_2102_05054_amd import kicked_ising
-    from workloads import config_kicked_ising
-
+    t_start = time.perf_counter()
     if args.scan_L is not None:
         scan(args.scan_L)
         return
@@ -530,9 +585,26 @@ def main():
     if args.workload == "bw_paper":
         brickwork_paper(args)
         return
+    if args.workload == "nominal":
+        nominal(args)
+        return
+    from workloads import config_kicked_ising
     L = args.L
     k = args.k if args.k is not None else int(math.floor(0.8 * 2 ** (L + 1) / args.ncv))
     p = config_kicked_ising("ki_L20", W=args.W, L=L)
+    # the host baseline runs first, before anything touches the GPU (its
+    # worker processes are started from a process without a HIP context)
+    cpu = None
+    if not (args.no_cpu or args.profile_gemm or args.profile_filter):
+        try:
+            cpu = cpu_baseline(p)
+        except Exception as e:  # reported, never fatal for the GPU measurement
+            cpu = {"error": f"{type(e).__name__}: {e}"}
+        log(f"cpu baseline: {cpu.get('value', 0):.2f} U-applications/s")
+
+    import torch
+
+    from paper_2102_05054_amd import kicked_ising
     op = kicked_ising(p.L, p.J, p.h, p.g, p.periodic)
     d = 2 ** L
 
@@ -555,27 +627,40 @@ def main():
         torch.cuda.synchronize()
         return time.perf_counter() - t0, ev, res, st, status
 
-    for _ in range(args.warmup):
-        solve("c64", args.block)
-    torch.cuda.synchronize()
+    # Wall budget: one warm-up solve at most (it also runs the tile tuner),
+    # then timed solves while the rest still fits: the complex128 comparison
+    # solve, the roofline passes and the JSON line need about one more solve.
+    warm = min(args.warmup, 1)
+    for _ in range(warm):
+        dt, *_ = solve("c64", args.block)
+        log(f"warm-up c64+refine solve: {dt:.1f} s")
     t_total = 0.0
     uapps = 0
     runs = []
-    for _ in range(args.steps):
+    for i in range(args.steps):
         dt, ev, res, st, status = solve("c64", args.block)
-        print(f"[bench] c64+refine solve: {dt:.1f} s, status {int(status)}", file=sys.stderr, flush=True)
+        log(f"c64+refine solve {i + 1}: {dt:.1f} s, status {int(status)}")
         t_total += dt
         uapps += st["n_U_apps"]
-        runs.append((dt, res, st, status))
-    last_dt, last_res, last_st, last_status = runs[-1]
+        runs.append((dt, ev, res, st, status))
+        elapsed = time.perf_counter() - t_start
+        if elapsed + dt * (1.0 + 2.2) + 30.0 > args.budget:
+            break
+    last_dt, last_ev, last_res, last_st, last_status = runs[-1]
+    steps_done = len(runs)
 
     c128 = None
     if not args.no_c128:
         dt2, ev2, res2, st2, status2 = solve("c128", args.block_c128)
-        print(f"[bench] c128 solve: {dt2:.1f} s, status {int(status2)}", file=sys.stderr, flush=True)
+        log(f"c128 solve: {dt2:.1f} s, status {int(status2)}")
+        # the two precisions must return the same eigenvalue set
+        a = np.sort_complex(np.asarray(last_ev))
+        b = np.sort_complex(np.asarray(ev2))
         c128 = {"time_s": dt2, "status": int(status2), "nconv": st2["nconv"], "max_residual": float(res2.max()),
                 "n_U_apps": st2["n_U_apps"], "n_restarts": st2["n_restarts"], "t_filter_s": st2["t_filter"],
-                "block": args.block_c128}
+                "block": args.block_c128,
+                "max_eigenvalue_difference_to_c64_refine": float(np.max(np.abs(a - b))) if a.shape == b.shape
+                else None}
 
     # the refinement's complex128 passes or the complex64 passes: whichever
     # phase took longer in the timed solve bounds it
@@ -583,8 +668,15 @@ def main():
     dom = "c128" if t_ref > 0.5 * last_dt else "c64"
     roof = filter_roofline(op, L, args.roofline_steps, args.block, dom)
     other = filter_roofline(op, L, args.roofline_steps, args.block, "c64" if dom == "c128" else "c128")
-    print(f"[bench] roofline: {roof['avg_launch_us']:.2f} us per {dom} pass", file=sys.stderr, flush=True)
-    cpu = None if args.no_cpu else cpu_baseline(p)
+    log(f"roofline: {roof['avg_launch_us']:.2f} us per {dom} pass")
+    op.close()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    try:
+        hbm = pass_roofline_L24()
+        log(f"L=24 passes: c64 {hbm['c64']['avg_launch_us']:.1f} us, c128 {hbm['c128']['avg_launch_us']:.1f} us")
+    except Exception as e:
+        hbm = {"error": f"{type(e).__name__}: {e}"}
 
     value = uapps / t_total
     line = {
@@ -592,9 +684,9 @@ def main():
         "value": value,
         "unit": "U-applications/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * t_total / args.steps,
+        "steps": steps_done,
+        "warmup": warm,
+        "ms_per_step": 1e3 * t_total / steps_done,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -603,17 +695,21 @@ def main():
         "config": {
             "workload": f"kicked Ising L={L} (d={d}), W={args.W}, nev={args.nev}, ncv={args.ncv}, "
                         f"k={k} (paper rule 0.8*2^(L+1)/ncv), phi=0, tol={args.tol}, "
-                        f"block Krylov-Schur with {args.block} vectors per filter launch",
+                        f"block Krylov-Schur with {args.block} vectors per filter launch; one step = one "
+                        f"complete solve",
             "L": L, "nev": args.nev, "ncv": args.ncv, "k": k, "phi": 0.0, "block": args.block,
         },
-        "time_to_eigenpairs_s": {"c64+refine": last_dt, "c128": c128["time_s"] if c128 else None},
-        "eigenpairs_per_s": {"c64+refine": args.nev / last_dt,
+        "steps_requested": args.steps,
+        "warmup_requested": args.warmup,
+        "budget_s": args.budget,
+        "time_to_eigenpairs_s": {"c64+refine": t_total / steps_done, "c128": c128["time_s"] if c128 else None},
+        "eigenpairs_per_s": {"c64+refine": args.nev * steps_done / t_total,
                              "c128": (args.nev / c128["time_s"]) if c128 else None},
         "solve": {"status": int(last_status), "nconv": last_st["nconv"], "max_residual": float(last_res.max()),
                   "n_restarts": last_st["n_restarts"], "n_U_apps": last_st["n_U_apps"],
                   "n_U_apps_c64": last_st["n_U_apps_c64"], "t_refine_s": last_st["t_refine"],
                   "t_filter_s": last_st["t_filter"], "t_orth_s": last_st["t_orth"],
-                  "t_restart_s": last_st["t_restart"]},
+                  "t_restart_s": last_st["t_restart"], "step_times_s": [r[0] for r in runs]},
         "c128_solve": c128,
         "roofline": {
             "bound": "hbm",
@@ -636,10 +732,55 @@ def main():
             "bytes_per_launch": other["bytes_per_launch"],
             "traffic": traffic_per_pass(args.block, other["dtype"]),
         },
+        "roofline_L24_hbm_resident": hbm,
         "cpu_baseline": cpu,
+        "wall_s": time.perf_counter() - t_start,
     }
-    op.close()
-    print(json.dumps(line))
+    print(json.dumps(line), flush=True)
+
+
+def nominal(args):
+    """The configurations at their nominal filter orders, reported as they
+    end (converged or not): L = 16 complex128, k = 200, nev = 50, ncv = 120,
+    phi drawn, one vector per step; L = 20, k = 400, nev = 100, ncv = 220,
+    W in {1, 3}, complex64 + FP64 refinement (block 4) and complex128
+    (block 2).  Each solve stops after --max-restarts restarts; status,
+    converged pairs and the largest FP64 residual are printed per solve."""
+    import torch
+
+    from paper_2102_05054_amd import kicked_ising
+    from workloads import CONFIGS, config_kicked_ising
+    rows = []
+
+    def run(name, p, nev, ncv, k, dtype, block, phi):
+        with kicked_ising(p.L, p.J, p.h, p.g, p.periodic) as op:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ev, _, res, st, status = op.arnoldi_eigs(nev, phi, k=k, ncv=ncv, tol=1e-10,
+                                                     max_restarts=args.max_restarts, filter_dtype=dtype,
+                                                     seed=1, want_vectors=False, allow_not_converged=True,
+                                                     block=block)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        r = {"case": name, "L": p.L, "k": k, "nev": nev, "ncv": ncv, "dtype": dtype, "block": block,
+             "status": int(status), "nconv": st["nconv"], "max_residual": float(res.max()),
+             "n_restarts": st["n_restarts"], "n_U_apps": st["n_U_apps"], "time_s": dt}
+        rows.append(r)
+        print(json.dumps(r), flush=True)
+
+    c2 = CONFIGS["ki_L16"]
+    p2 = config_kicked_ising("ki_L16")
+    run("ki_L16 nominal", p2, c2["nev"], c2["ncv"], c2["k"], "c128", 1, p2.phi)
+    c3 = CONFIGS["ki_L20"]
+    for W in c3["W"]:
+        p3 = config_kicked_ising("ki_L20", W=W)
+        for dtype, block in (("c64", 4), ("c128", 2)):
+            run(f"ki_L20 W={W:g} nominal", p3, c3["nev"], c3["ncv"], c3["k"], dtype, block, 0.0)
+    print(json.dumps({"nominal": rows, "max_restarts": args.max_restarts}))
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 if __name__ == "__main__":

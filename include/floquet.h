@@ -144,8 +144,12 @@ fq_status apply_polynomial(floquet_op* op, int k, const double* coeffs_host, fq_
 
 /* Options of arnoldi_eigs. */
 typedef struct {
-  int k;                   /* filter order (>= 0) */
-  int ncv;                 /* Krylov dimension, nev + 2 <= ncv <= min(d, 3000) */
+  int k;                   /* filter order (>= 0).  0 without poly_coeffs: the paper's rule
+                              k = floor(0.8 * 2^(L+1) / ncv) for the ncv used (Sec. 5, Table
+                              "bench" caption; fq_paper_parameters) */
+  int ncv;                 /* Krylov dimension, nev + 2 <= ncv <= min(d, 3000).  0: the paper's
+                              rule n_cv = floor(2^(L/2+1)), at least 2 nev + 1, below d, capped
+                              at 3000 (arnoldi_eigs only; arnoldi_eigs_batched needs ncv > 0) */
   double tol;              /* residual tolerance on ||U v - omega v|| */
   int max_restarts;        /* Krylov-Schur restarts before FQ_NOT_CONVERGED */
   fq_dtype filter_dtype;   /* FQ_C64: filter in complex64, rest FP64 */
@@ -192,7 +196,10 @@ typedef struct {
  * destroy_floquet_op).  Returns FQ_NOT_CONVERGED (results valid for the
  * first stats.nconv pairs) when max_restarts is reached, FQ_ENOMEM when the
  * workspace does not fit, FQ_EINVAL for nev < 1, ncv < nev + 2, ncv > min(d, 3000),
- * k < 0 or tol <= 0.
+ * k < 0 or tol <= 0, FQ_ENUMERIC for NaN/Inf in the filter output or a Krylov
+ * space that becomes invariant with fewer than nev vectors.  A space that
+ * becomes invariant with at least nev vectors (ncv = d, or fewer distinct
+ * filter values than ncv) is analysed as it stands: its Ritz pairs are exact.
  */
 fq_status arnoldi_eigs(floquet_op* op, int nev, double phi, const fq_arnoldi_opts* opts,
                        double* evals_host, void* evecs_dev, double* resid_host,
@@ -238,7 +245,8 @@ fq_status entanglement_entropy(const floquet_op* op, int LA, const void* states_
 /*
  * The paper's parameter rule for large L (Sec. 5 and the caption of Table
  * "bench"): n_cv = floor(2^(L/2 + 1)), raised to at least 2*nev + 1 (Sec. 4:
- * n_cv > 2 n_ev), and k = floor(0.8 * 2^(L+1) / n_cv), the Krylov dimension
+ * n_cv > 2 n_ev) and lowered to at most 2^L - 1 (a Krylov space of dimension
+ * 2^L is the whole space), and k = floor(0.8 * 2^(L+1) / n_cv), the Krylov dimension
  * sitting at 80% of the eigenvalue count on the outer "apple" line of
  * g_k (Sec. 3, last paragraph).  Host-only; returns FQ_EINVAL for L outside
  * [2, 30] or nev < 1.

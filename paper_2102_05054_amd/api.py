@@ -132,12 +132,14 @@ class FloquetOp:
                                      _stream_ptr(stream)), "apply_polynomial")
         return out
 
-    def arnoldi_eigs(self, nev: int, phi: float, *, k: int, ncv: int, tol: float = 1e-10,
+    def arnoldi_eigs(self, nev: int, phi: float, *, k: int = 0, ncv: int = 0, tol: float = 1e-10,
                      max_restarts: int = 200, filter_dtype: str = "c128", refine: bool = True,
                      seed: int = 0, v0=None, want_vectors: bool = True, stream=None,
                      allow_not_converged: bool = False, refine_k: int = 0, poly=None, block: int = 1):
         """Eigenpairs of U closest to e^{i phi}.  Returns (evals, evecs, resid, stats, status).
 
+        ``k = 0`` / ``ncv = 0`` select the paper's rule (fq_paper_parameters: n_cv =
+        floor(2^(L/2+1)), k = floor(0.8 * 2^(L+1) / n_cv) for the n_cv used).
         ``poly`` (optional): coefficients a_0..a_k of the filter sum_m a_m U^m used
         instead of the geometric sum (k is then len(poly) - 1).
         ``block`` (1, 2, 4 or 8): vectors filtered per Krylov step (block Krylov-Schur)."""
@@ -223,13 +225,14 @@ def circuit(L: int, sites, widths, gates) -> FloquetOp:
     return FloquetOp(desc, keep=(flat, sa, wa))
 
 
-def arnoldi_eigs_batched(ops: Sequence[FloquetOp], phis: Sequence[float], nev: int, *, k, ncv: int,
+def arnoldi_eigs_batched(ops: Sequence[FloquetOp], phis: Sequence[float], nev: int, *, k=0, ncv: int,
                          tol: float = 1e-10, max_restarts: int = 200, filter_dtype: str = "c128",
                          refine: bool = True, seed: int = 0, want_vectors: bool = False, stream=None,
                          allow_not_converged=False, refine_k: int = 0, poly=None):
     """All (op, phi) problems in one call.
 
-    ``k`` is one filter order for every op or a sequence with one per op.
+    ``k`` is one filter order for every op or a sequence with one per op;
+    ``k = 0`` selects the paper's rule per chain length for the given ncv.
     Returns (evals[n_ops, n_phi, nev], resid, stats, status), plus the
     eigenvectors (list over problems of (nev, d) complex128 device tensors)
     when ``want_vectors``.

@@ -58,6 +58,55 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
+# ---------------------------------------------------------------------------
+# Host mock of the device layer (test infrastructure, no GPU): the Krylov-Schur
+# driver sources compiled with g++ against hostmock/ (a host stand-in for the
+# HIP runtime and the kernels, with a diagonal mock operator), as a shared
+# library for the CPU tests and as a self-test executable built with the
+# address and undefined-behaviour sanitizers.  Neither is part of libfloquet.so.
+# ---------------------------------------------------------------------------
+MOCK_DIR = os.path.join(HERE, "hostmock")
+MOCK_LIB = os.path.join(MOCK_DIR, "libfloquet_hostmock.so")
+MOCK_SELFTEST = os.path.join(BUILD, "hostmock_selftest_asan")
+MOCK_DRIVER_SOURCES = ["krylov.cpp", "block.cpp", "dense.cpp"]
+MOCK_FLAGS = ["-std=c++17", "-Wall", "-Wno-unused-function", "-fcx-limited-range",
+              "-I", MOCK_DIR, "-I", os.path.join(ROOT, "include")]
+
+
+def _gxx(args):
+    r = subprocess.run(["g++", *args], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"g++ failed: g++ {' '.join(args)}\n{r.stdout}\n{r.stderr}")
+
+
+def mock_sources():
+    return [os.path.join(CSRC, f) for f in MOCK_DRIVER_SOURCES] + [os.path.join(MOCK_DIR, "hostmock.cpp")]
+
+
+def build_hostmock(verbose: bool = True) -> str:
+    """libfloquet_hostmock.so: the driver on the host mock (plain build)."""
+    os.makedirs(BUILD, exist_ok=True)
+    tmp = MOCK_LIB + ".tmp"
+    _gxx([*MOCK_FLAGS, "-O1", "-g", "-fPIC", "-shared", *mock_sources(), "-o", tmp])
+    os.replace(tmp, MOCK_LIB)
+    if verbose:
+        print(f"built {MOCK_LIB}")
+    return MOCK_LIB
+
+
+def build_hostmock_selftest(verbose: bool = True) -> str:
+    """The driver on the host mock under AddressSanitizer + UBSan (host code
+    only, nothing for the GPU), with the scenario driver hostmock/selftest.cpp."""
+    os.makedirs(BUILD, exist_ok=True)
+    tmp = MOCK_SELFTEST + ".tmp"
+    _gxx([*MOCK_FLAGS, "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+          "-fno-sanitize-recover=all", *mock_sources(), os.path.join(MOCK_DIR, "selftest.cpp"), "-o", tmp])
+    os.replace(tmp, MOCK_SELFTEST)
+    if verbose:
+        print(f"built {MOCK_SELFTEST}")
+    return MOCK_SELFTEST
+
+
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
@@ -71,6 +120,8 @@ def build(verbose: bool = True) -> str:
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB}")
+    build_hostmock(verbose)
+    build_hostmock_selftest(verbose)
     return LIB
 
 

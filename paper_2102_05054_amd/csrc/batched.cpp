@@ -796,7 +796,8 @@ fq_status arnoldi_batched_solve(floquet_op* const* ops, int n_ops, const double*
   std::vector<int> ks(n_ops);
   for (int i = 0; i < n_ops; ++i) {
     fq_arnoldi_opts oi = *o;
-    ks[i] = k_per_op ? k_per_op[i] : o->k;
+    // k = 0 without a user polynomial: the paper's rule for this chain length
+    ks[i] = k_per_op ? k_per_op[i] : ((o->k == 0 && !o->poly_coeffs && ops[i] && o->ncv > 0) ? paper_k(ops[i]->L, o->ncv) : o->k);
     oi.k = ks[i];
     FQ_TRY(validate_arnoldi(ops[i], nev, &oi));
     if (ks[i] < 1) {

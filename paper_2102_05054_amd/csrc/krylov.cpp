@@ -336,8 +336,11 @@ struct Solver {
             return FQ_ENUMERIC;
           }
           if (beta <= 1e-14 * std::max(hn, 1e-300)) {
-            set_error("Arnoldi breakdown: the Krylov space became invariant before ncv vectors");
-            return FQ_ENUMERIC;
+            // The Krylov space is invariant: g V = V H holds exactly for the
+            // first jj + 1 columns (e.g. ncv = d, or a spectrum with fewer
+            // distinct filter values than ncv).  Its Ritz pairs are exact.
+            H(jj + 1, jj) = 0.0;
+            return finish_invariant(H, jj + 1, tolg, tol, check_true, res);
           }
           H(jj + 1, jj) = beta;
         }
@@ -422,6 +425,29 @@ struct Solver {
     }
   }
 
+  // Ritz pairs of an invariant Krylov space of dimension mm (its residual
+  // row is zero, so every Ritz estimate vanishes).
+  fq_status finish_invariant(const ZMat& H, int mm, double tolg, double tol, bool check_true, PhaseResult* res) {
+    if (mm < nev) {
+      set_error("Arnoldi breakdown: the Krylov space became invariant at dimension " + std::to_string(mm) +
+                " < nev (the start vector meets fewer than nev eigenvectors, or the spectrum is degenerate)");
+      return FQ_ENUMERIC;
+    }
+    ZMat Hs(mm + 1, mm);
+    for (int j = 0; j < mm; ++j)
+      for (int i = 0; i < mm; ++i) Hs(i, j) = H(i, j);
+    ZMat T, Z, X;
+    std::vector<zd> bz;
+    int nconv = 0;
+    double worst = 0.0;
+    FQ_TRY(analyse(Hs, mm, nev, tolg, &T, &Z, &bz, &X, &nconv, &worst));
+    FQ_TRY(ritz_and_residuals(op, ws, mm, X, nev, &res->ritz, s, &st->n_U_apps));
+    double rmax = 0.0;
+    for (double r : res->ritz.resid) rmax = std::max(rmax, r);
+    res->converged = check_true ? rmax <= tol : true;
+    return FQ_OK;
+  }
+
   fq_status analyse(const ZMat& H, int mm, int nsort, double tolg, ZMat* T, ZMat* Z, std::vector<zd>* bz, ZMat* X,
                     int* nconv, double* worst) {
     const double t2 = now_s();
@@ -476,8 +502,36 @@ fq_status poly_scale_copy(floquet_op* op, zd a, fq_dtype dt, const void* psi, vo
   return FQ_OK;
 }
 
-fq_status arnoldi_solve(floquet_op* op, int nev, double phi, const fq_arnoldi_opts* o, double* evals_host,
+int paper_ncv(int L, int nev) {
+  const double d = std::ldexp(1.0, L);
+  long long ncv = static_cast<long long>(std::floor(std::pow(2.0, L / 2.0 + 1.0)));
+  ncv = std::max<long long>(ncv, 2LL * nev + 1);
+  // below d: a Krylov space of dimension d is the whole space
+  ncv = std::min<long long>(ncv, static_cast<long long>(d) - 1);
+  return static_cast<int>(ncv);
+}
+
+int paper_k(int L, int ncv) {
+  const long long k = static_cast<long long>(std::floor(0.8 * 2.0 * std::ldexp(1.0, L) / double(ncv)));
+  return static_cast<int>(std::max<long long>(k, 1));
+}
+
+fq_arnoldi_opts resolve_auto(const floquet_op* op, int nev, const fq_arnoldi_opts* o) {
+  fq_arnoldi_opts r = *o;
+  if (!op) return r;
+  if (r.ncv == 0) r.ncv = std::min(paper_ncv(op->L, nev), 3000);
+  if (r.k == 0 && !r.poly_coeffs && r.ncv > 0) r.k = paper_k(op->L, r.ncv);
+  return r;
+}
+
+fq_status arnoldi_solve(floquet_op* op, int nev, double phi, const fq_arnoldi_opts* o_in, double* evals_host,
                         void* evecs_dev, double* resid_host, fq_arnoldi_stats* stats, hipStream_t s) {
+  if (!o_in) {
+    set_error("opts is NULL");
+    return FQ_EINVAL;
+  }
+  const fq_arnoldi_opts oo = resolve_auto(op, nev, o_in);
+  const fq_arnoldi_opts* o = &oo;
   FQ_TRY(validate_arnoldi(op, nev, o));
   if (o->block > 1) return block_solve(op, nev, phi, o, evals_host, evecs_dev, resid_host, stats, s);
   const double t_start = now_s();
@@ -626,13 +680,8 @@ fq_status fq_paper_parameters(int L, int nev, int* ncv_out, int* k_out) {
     set_error("fq_paper_parameters: need 2 <= L <= 30, nev >= 1 and output pointers");
     return FQ_EINVAL;
   }
-  const double d = std::ldexp(1.0, L);
-  long long ncv = static_cast<long long>(std::floor(std::pow(2.0, L / 2.0 + 1.0)));
-  ncv = std::max<long long>(ncv, 2LL * nev + 1);
-  ncv = std::min<long long>(ncv, static_cast<long long>(d));
-  const long long k = static_cast<long long>(std::floor(0.8 * 2.0 * d / double(ncv)));
-  *ncv_out = static_cast<int>(ncv);
-  *k_out = static_cast<int>(std::max<long long>(k, 1));
+  *ncv_out = paper_ncv(L, nev);
+  *k_out = paper_k(L, *ncv_out);
   return FQ_OK;
 }
 

@@ -18,6 +18,16 @@ namespace fq {
 fq_status analyse_decomposition(const ZMat& H, int mm, int nsort, int nev, double tolg, ZMat* T, ZMat* Z,
                                 std::vector<zd>* bz, ZMat* X, int* nconv, double* worst);
 
+// The paper's parameter rule (Sec. 5, caption of Table "bench"): n_cv =
+// floor(2^(L/2+1)), at least 2 nev + 1 and below d; k = floor(0.8 2^(L+1) / n_cv),
+// at least 1.
+int paper_ncv(int L, int nev);
+int paper_k(int L, int ncv);
+
+// Options with ncv = 0 / k = 0 (no user polynomial) replaced by the rule
+// (ncv also capped at 3000).
+fq_arnoldi_opts resolve_auto(const floquet_op* op, int nev, const fq_arnoldi_opts* o);
+
 // Argument checks shared by arnoldi_eigs and arnoldi_eigs_batched.
 fq_status validate_arnoldi(const floquet_op* op, int nev, const fq_arnoldi_opts* o);
 

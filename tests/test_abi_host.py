@@ -102,6 +102,14 @@ def test_paper_parameter_rule(L, nev):
         assert (ncv, k) == (2048, 819)
 
 
+@pytest.mark.parametrize("L,nev,expect", [(2, 1, (3, 2)), (4, 8, (15, 1)), (6, 40, (63, 1)), (8, 10, (32, 12))])
+def test_paper_parameter_rule_small_chains(L, nev, expect):
+    # n_cv is raised to 2 nev + 1 but kept below d = 2^L: a Krylov space of
+    # dimension d is the whole space (the last Arnoldi step would break down)
+    from paper_2102_05054_amd import paper_parameters
+    assert paper_parameters(L, nev) == expect
+
+
 @pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (5, 2), (64, 3), (300, 4)])
 def test_host_hermitian_eigenvalues_against_lapack(n, seed):
     # the eigenvalue step of entanglement_entropy (Householder + implicit QL)

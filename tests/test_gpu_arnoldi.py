@@ -135,3 +135,30 @@ def test_wide_restart_rotation_against_dense():
     assert status == 0
     assert np.max(np.abs(ev - om_ref)) < 1e-12
     assert res.max() <= 1e-10
+
+
+@pytest.mark.parametrize("L,nev,phi", [(10, 20, 0.0), (12, 30, 2.4)])
+@pytest.mark.parametrize("filter_dtype,block", [("c128", 1), ("c64", 4)])
+def test_paper_rule_defaults_match_zgeev(L, nev, phi, filter_dtype, block):
+    # k = 0, ncv = 0: n_cv = floor(2^(L/2+1)) and k = floor(0.8 * 2^(L+1) / n_cv)
+    # (Sec. 5, Table "bench" caption), against full diagonalisation
+    say(f"paper-rule defaults L={L} {filter_dtype} block {block}")
+    p = kicked_ising(L, 60 + L)
+    U = models.ki_dense(p)
+    om_ref, _ = eig.full_closest(U, nev, phi)
+    ncv = max(int(math.floor(2 ** (L / 2 + 1))), 2 * nev + 1)
+    k = int(math.floor(0.8 * 2 ** (L + 1) / ncv))
+    with ki_op(p) as op:
+        ev, vecs, res, stats, st = op.arnoldi_eigs(nev, phi, tol=1e-10, filter_dtype=filter_dtype, seed=4,
+                                                   block=block)
+        vecs = to_np(vecs)
+    say(stats)
+    assert st == 0
+    assert np.max(np.abs(ev - om_ref)) < 1e-12
+    assert res.max() <= 1e-10
+    assert (stats["n_U_apps"] - stats["n_U_apps_c64"]) >= 0
+    # every filter application is k U-applications; the rest are the nev
+    # residual checks of each convergence test
+    assert (stats["n_U_apps"] - stats["n_filter_apps"] * k) % nev == 0
+    for n in range(nev):
+        assert np.linalg.norm(U @ vecs[n] - ev[n] * vecs[n]) < 1e-10

@@ -1,0 +1,204 @@
+"""GPU parity of the full-size eigen-solves.
+
+* The L = 20 solve (nev = 100, ncv = 220, k by the paper's rule) in both forms
+  the benchmark times: complex64 filter + FP64 refinement with 4 vectors per
+  filter launch, and plain complex128 with 2.  Every returned pair is
+  re-checked with the oracle's matrix-free U (Sec. 4, Eq. (residual)), and the
+  two precisions must return the same eigenvalue set.
+* Completeness at L = 16 and L = 20 on the closed-form special cases of the
+  kicked-Ising chain (g = 0: U diagonal; g = pi/2: U pairs each basis state
+  with its complement), where the full spectrum is known: the solver must
+  return exactly the n_ev eigenvalues closest to e^{i phi} (the problem
+  statement opening Sec. 3).
+* The L = 16 configuration as specified (complex128, k = 200, one vector per
+  step, phi drawn), every residual re-checked by the oracle.
+"""
+
+import cmath
+import concurrent.futures as cf
+import math
+
+import numpy as np
+import pytest
+
+from gpu_util import ki_op, say, to_np
+from oracle import eig, models
+from workloads import CONFIGS, config_kicked_ising, kicked_ising
+
+pytestmark = pytest.mark.gpu
+
+
+def paper_k(L, ncv):
+    return int(math.floor(0.8 * 2 ** (L + 1) / ncv))
+
+
+def oracle_residuals(p, evals, vecs):
+    """||U v - omega v|| with the oracle's matrix-free U, several vectors at a
+    time on host threads (NumPy releases the GIL inside its loops)."""
+    def one(n):
+        return float(np.linalg.norm(models.ki_apply(p, vecs[n]) - evals[n] * vecs[n]))
+    with cf.ThreadPoolExecutor(max_workers=8) as ex:
+        return np.array(list(ex.map(one, range(len(evals)))))
+
+
+def by_angle(ev):
+    ev = np.asarray(ev)
+    return ev[np.argsort(np.angle(ev))]
+
+
+def assert_same_set(a, b, tol):
+    a, b = np.asarray(a), np.asarray(b)
+    assert a.shape == b.shape
+    for x in a:
+        assert np.min(np.abs(b - x)) < tol, (x, np.min(np.abs(b - x)))
+    for x in b:
+        assert np.min(np.abs(a - x)) < tol, (x, np.min(np.abs(a - x)))
+
+
+def check_sorted_by_distance(ev, phi):
+    dist = eig.arc_distance(ev, phi)
+    assert np.all(np.diff(dist) >= -1e-13)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("W", [1.0, 3.0])
+def test_headline_L20_both_precisions(W):
+    c = CONFIGS["ki_L20"]
+    nev, ncv = c["nev"], c["ncv"]
+    p = config_kicked_ising("ki_L20", W=W)
+    k = paper_k(p.L, ncv)
+    out = {}
+    with ki_op(p) as op:
+        for dtype, block in (("c64", 4), ("c128", 2)):
+            say(f"headline L=20 W={W} {dtype} block {block} k={k}")
+            ev, vecs, res, st, status = op.arnoldi_eigs(nev, 0.0, k=k, ncv=ncv, tol=1e-10, filter_dtype=dtype,
+                                                        seed=1, block=block, max_restarts=60)
+            say(st)
+            assert status == 0 and st["nconv"] == nev
+            assert res.max() <= 1e-10
+            vecs = to_np(vecs)
+            r = oracle_residuals(p, ev, vecs)
+            say(f"  oracle residuals: max {r.max():.2e}")
+            assert r.max() <= 1e-10
+            assert np.max(np.abs(np.abs(ev) - 1.0)) <= 1e-10
+            check_sorted_by_distance(ev, 0.0)
+            # unit-norm, mutually orthogonal eigenvectors (U is unitary, the
+            # eigenvalues are distinct)
+            G = vecs.conj() @ vecs.T
+            assert np.max(np.abs(G - np.eye(nev))) < 1e-8
+            out[dtype] = ev
+            del vecs
+    assert_same_set(out["c64"], out["c128"], 1e-12)
+
+
+def closed_form_spectrum(p):
+    """Full spectrum of the kicked-Ising U at g = 0 or g = pi/2 from the
+    oracle's energies E(s) (the two special cases of the model: at g = 0,
+    U = diag e^{-iE(s)}; at g = pi/2 the kick is (-i)^L X^{(x)L} and U has
+    eigenvalues +-(-i)^L e^{-i(E(s)+E(s'))/2} on each pair (s, s'), s' the
+    complement of s)."""
+    L = p.L
+    d = 2 ** L
+    E = models.ki_energies(L, p.J, p.h, p.periodic)
+    if p.g == 0.0:
+        return np.exp(-1j * E)
+    assert abs(p.g - math.pi / 2) < 1e-15
+    s = np.arange(d // 2)  # one member of each pair: the top bit clear
+    sc = (d - 1) ^ s
+    base = (-1j) ** L * np.exp(-0.5j * (E[s] + E[sc]))
+    return np.concatenate([base, -base])
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("g", [0.0, math.pi / 2])
+@pytest.mark.parametrize("L,dtype,block", [(16, "c128", 1), (16, "c64", 4), (20, "c128", 2), (20, "c64", 4)])
+def test_completeness_closed_form(L, dtype, block, g):
+    if L == 16:
+        c = CONFIGS["ki_L16"]
+        base = config_kicked_ising("ki_L16")
+    else:
+        c = CONFIGS["ki_L20"]
+        base = config_kicked_ising("ki_L20", W=1.0)
+    nev, ncv, phi = c["nev"], c["ncv"], base.phi
+    p = kicked_ising(L, c["seed"], g=g, phi=phi, h_range=(-1.0, 1.0) if L == 20 else (-2.0, 2.0))
+    k = paper_k(L, ncv)
+    spec = closed_form_spectrum(p)
+    dist = eig.arc_distance(spec, phi)
+    order = np.argsort(dist, kind="stable")
+    expect = spec[order[:nev]]
+    # the boundary pair of the wanted set must be separated (c6: a near tie
+    # would allow either member)
+    assert dist[order[nev]] - dist[order[nev - 1]] > 1e-9
+    say(f"completeness L={L} g={g:.4f} {dtype} block {block} k={k} phi={phi:.4f}")
+    with ki_op(p) as op:
+        ev, vecs, res, st, status = op.arnoldi_eigs(nev, phi, k=k, ncv=ncv, tol=1e-10, filter_dtype=dtype,
+                                                    seed=2, block=block, max_restarts=60,
+                                                    want_vectors=(L == 16))
+    say(st)
+    assert status == 0
+    assert res.max() <= 1e-10
+    assert_same_set(ev, expect, 1e-12)
+    check_sorted_by_distance(ev, phi)
+    if L == 16:
+        v = to_np(vecs)
+        d = 2 ** L
+        for n in range(nev):
+            a2 = np.abs(v[n]) ** 2
+            if g == 0.0:
+                # a basis state
+                assert a2.max() > 1 - 1e-10
+            else:
+                # supported on one complementary pair
+                s = int(np.argmax(a2))
+                assert a2[s] + a2[(d - 1) ^ s] > 1 - 1e-10
+        r = oracle_residuals(p, ev, v)
+        assert r.max() <= 1e-10
+
+
+@pytest.mark.timeout(300)
+def test_ki_L16_as_configured():
+    # complex128, k = 200, one vector per Krylov step, phi drawn; the same set
+    # as the complex64 + FP64 solve at the paper's order with blocks of 4
+    c = CONFIGS["ki_L16"]
+    p = config_kicked_ising("ki_L16")
+    say(f"ki_L16 as configured: k={c['k']} phi={p.phi:.4f}")
+    with ki_op(p) as op:
+        ev, vecs, res, st, status = op.arnoldi_eigs(c["nev"], p.phi, k=c["k"], ncv=c["ncv"], tol=1e-10,
+                                                    filter_dtype="c128", seed=1, block=1, max_restarts=200)
+        say(st)
+        ev4, _, res4, st4, status4 = op.arnoldi_eigs(c["nev"], p.phi, k=paper_k(p.L, c["ncv"]), ncv=c["ncv"],
+                                                     tol=1e-10, filter_dtype="c64", seed=1, block=4,
+                                                     want_vectors=False)
+        vecs = to_np(vecs)
+    assert status == 0 and st["nconv"] == c["nev"]
+    assert status4 == 0
+    r = oracle_residuals(p, ev, vecs)
+    assert r.max() <= 1e-10
+    assert np.max(np.abs(np.abs(ev) - 1.0)) <= 1e-10
+    check_sorted_by_distance(ev, p.phi)
+    assert_same_set(ev, ev4, 1e-12)
+
+
+def test_ki_L20_filter_many_elementwise():
+    # the complex64 launches of the L = 20 solve: 4 and 8 vectors per pass,
+    # element-wise against the oracle's geometric sum
+    from gpu_util import require_gpu, to_dev
+    from oracle import filters
+    from workloads import random_state
+    torch = require_gpu()
+    p = config_kicked_ising("ki_L20", W=1.0)
+    k, phi = 5, 0.4
+    psi = random_state(2 ** 20, 77, 8)
+
+    def ref_one(j):
+        return filters.geometric_sum(lambda v: models.ki_apply(p, v), psi[j], k, phi)
+    with cf.ThreadPoolExecutor(max_workers=8) as ex:
+        ref = np.stack(list(ex.map(ref_one, range(8))))
+    tol = 2e-7 * (k + 1) + 2e-6
+    with ki_op(p) as op:
+        for n in (4, 8):
+            say(f"apply_filter_many L=20 c64 n={n}")
+            out = to_np(op.apply_filter_many(to_dev(psi[:n], torch.complex64), k, phi))
+            for j in range(n):
+                err = np.max(np.abs(out[j] - ref[j])) / np.max(np.abs(ref[j]))
+                assert err < tol, (n, j, err)

@@ -43,6 +43,27 @@ def test_full_diag_residuals_at_paper_level(which, L):
     assert np.allclose(rq, om[:5], atol=1e-12)
 
 
+def test_residual_and_rayleigh_of_a_mixed_vector_hand_example():
+    # Eq. (residual) on a vector that is NOT an eigenvector: U = diag(1, i),
+    # v = (cos a, sin a).  By hand: U v - 1 v = (0, (i - 1) sin a), so
+    # r = sqrt(2) sin a; the Rayleigh quotient is cos^2 a + i sin^2 a, and
+    # U v - omega v = sin a cos a (1 - i) (-sin a, cos a), norm sqrt(2) sin a cos a.
+    a = 0.1
+    U = np.diag([1.0, 1j])
+    v = np.array([math.cos(a), math.sin(a)], dtype=complex)
+    mv = lambda x: U @ x  # noqa: E731
+    r1 = eig.residuals(mv, np.array([1.0 + 0j]), v[:, None])
+    assert abs(r1[0] - math.sqrt(2) * math.sin(a)) < 1e-15
+    om = eig.rayleigh(mv, v)
+    assert abs(om - (math.cos(a) ** 2 + 1j * math.sin(a) ** 2)) < 1e-15
+    r2 = eig.residuals(mv, np.array([om]), v[:, None])
+    assert abs(r2[0] - math.sqrt(2) * math.sin(a) * math.cos(a)) < 1e-15
+    # one column per vector, in order; an exact eigenvector has residual 0
+    V = np.stack([v, np.array([0.0, 1.0 + 0j])], axis=1)
+    r3 = eig.residuals(mv, np.array([1.0 + 0j, 1j]), V)
+    assert abs(r3[0] - math.sqrt(2) * math.sin(a)) < 1e-15 and r3[1] == 0.0
+
+
 def test_filtered_eigenvalues_follow_closed_form():
     # Eigenvectors of U are eigenvectors of g_k(U) with eigenvalue g_k(omega) (Sec. 4).
     p = kicked_ising(7, 31)
