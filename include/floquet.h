@@ -134,6 +134,25 @@ fq_status apply_filter_many(floquet_op* op, int k, double phi, fq_dtype dtype, i
                             const void* psi_dev, void* out_dev, void* hip_stream);
 
 /*
+ * apply_filter_many without device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same out_j = g_k(U) psi_j for n_vec
+ * vectors, for kicked-Ising ops with L >= 4 only.  The launch descriptors and
+ * the phase tables for phi live in a fixed 4 MiB file-scope device array of
+ * the library (one per GPU, resolved on the first call on each device),
+ * refilled by two small kernels on hip_stream at every call; the passes are
+ * the plain batched ones with the tile shape the autotuner cached for this
+ * (L, precision, k, vector-count class), or the default shape (no timing, no
+ * trial launches).  Results agree with apply_filter_many to rounding.
+ * The op's device must be current.  Calls that overlap on one GPU (several
+ * streams or threads) race on the array.  Asynchronous on hip_stream.
+ * FQ_EINVAL for other models, L < 4, k < 0, non-finite phi, n_vec outside
+ * 1..64, overlapping buffers or another current device.
+ */
+fq_status apply_filter_many_noalloc(floquet_op* op, int k, double phi, fq_dtype dtype, int n_vec,
+                                    const void* psi_dev, void* out_dev, void* hip_stream);
+
+/*
  * out = sum_{m=0..k} a_m U^m psi, a general polynomial filter (Sec. 3,
  * Eq. (poly)), evaluated by Horner's rule w <- a_{m} psi + U w from w = a_k psi.
  * coeffs_host: k+1 complex128 coefficients a_0..a_k (interleaved re, im).

@@ -61,6 +61,7 @@ SIGNATURES = [
     ("apply_U", c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
     ("apply_filter", c_int, [c_void_p, c_int, c_double, c_int, c_void_p, c_void_p, c_void_p]),
     ("apply_filter_many", c_int, [c_void_p, c_int, c_double, c_int, c_int, c_void_p, c_void_p, c_void_p]),
+    ("apply_filter_many_noalloc", c_int, [c_void_p, c_int, c_double, c_int, c_int, c_void_p, c_void_p, c_void_p]),
     ("apply_polynomial", c_int, [c_void_p, c_int, POINTER(c_double), c_int, c_void_p, c_void_p, c_void_p]),
     ("arnoldi_eigs", c_int, [c_void_p, c_int, c_double, POINTER(FqArnoldiOpts), POINTER(c_double), c_void_p,
                              POINTER(c_double), POINTER(FqArnoldiStats), c_void_p]),

@@ -120,6 +120,18 @@ class FloquetOp:
                                       _dptr(psi), _dptr(out), _stream_ptr(stream)), "apply_filter_many")
         return out
 
+    def apply_filter_many_noalloc(self, psi, k: int, phi: float, out, stream=None):
+        """apply_filter_many without device allocation (kicked Ising, 1..64 vectors);
+        ``out`` must be given (the call allocates nothing)."""
+        if psi.dim() != 2 or psi.shape[1] != self.dim or not psi.is_cuda or not psi.is_contiguous():
+            raise ValueError(f"psi must be a contiguous (n_vec, {self.dim}) device tensor")
+        if out.shape != psi.shape or out.dtype != psi.dtype or not out.is_cuda or not out.is_contiguous():
+            raise ValueError("out must be a contiguous device tensor of psi's shape and dtype")
+        check(lib().apply_filter_many_noalloc(self.handle, int(k), float(phi), _dtype_code(psi), int(psi.shape[0]),
+                                              _dptr(psi), _dptr(out), _stream_ptr(stream)),
+              "apply_filter_many_noalloc")
+        return out
+
     def apply_polynomial(self, psi, coeffs: Sequence[complex], out=None, stream=None):
         """out = sum_m coeffs[m] U^m psi."""
         torch = _torch()

@@ -259,6 +259,49 @@ int size_class(unsigned n) {
 }
 }  // namespace
 
+template <typename Real>
+fq_status ki_batch_shape_untimed(int L, bool sw, int k, unsigned n, KiBatchShape* out) {
+  const bool c64_dt = sizeof(Real) == 4;
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tuned.find(std::make_tuple(L, sw, c64_dt, k, size_class(n)));
+    if (it != g_tuned.end()) {
+      *out = it->second;
+      return FQ_OK;
+    }
+  }
+  // the first candidate of ki_batch_candidates, built without containers
+  KiBatchShape c;
+  c.L = L;
+  c.m = (L + 1) / 2;
+  c.sw = sw;
+  if (L <= 13) {
+    int rb, tb;
+    single_shape(L, &rb, &tb);
+    if (L < 6) {
+      rb = 0;
+      tb = 6;
+    }
+    if (rb >= 0 && rb <= 4 && tb >= 6 && tb <= 9 && tb <= rb + 6 && shape_compiled(rb, tb)) {
+      c.single = true;
+      c.srb = rb;
+      c.stb = tb;
+      *out = c;
+      return FQ_OK;
+    }
+  }
+  c.plan = make_plan(L, c64_dt);
+  if (!plan_ok(c.plan, L)) {
+    set_error("no kicked-Ising tile shape for L = " + std::to_string(L));
+    return FQ_EINVAL;
+  }
+  *out = c;
+  return FQ_OK;
+}
+
+template fq_status ki_batch_shape_untimed<float>(int, bool, int, unsigned, KiBatchShape*);
+template fq_status ki_batch_shape_untimed<double>(int, bool, int, unsigned, KiBatchShape*);
+
 fq_status ki_set_policy(int policy) {
   if (policy != FQ_POLICY_AUTO && policy != FQ_POLICY_TILE && policy != FQ_POLICY_PIPE) {
     set_error("fq_set_kernel_policy: policy must be FQ_POLICY_AUTO, FQ_POLICY_TILE or FQ_POLICY_PIPE");

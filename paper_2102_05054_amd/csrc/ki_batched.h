@@ -64,4 +64,11 @@ fq_status ki_batch_tune(int L, bool sw, int k, const KiDesc<Real>* desc, const i
                         hipStream_t s, KiBatchShape* out, double* best_us, const KiDesc<Real>* chi0 = nullptr,
                         const KiDesc<Real>* chi1 = nullptr);
 
+// The shape ki_batch_tune would return, without timing anything (no events,
+// no trial launches): the cached tuner choice for this (L, kick form,
+// precision, k, batch size class) if there is one, otherwise the default
+// candidate (single workgroup for L <= 13, else the standard multi-pass plan).
+template <typename Real>
+fq_status ki_batch_shape_untimed(int L, bool sw, int k, unsigned n, KiBatchShape* out);
+
 }  // namespace fq
