@@ -63,12 +63,16 @@ def parse():
     ap.add_argument("--no-c128", action="store_true", help="skip the complex128 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--roofline-steps", type=int, default=2000)
+    ap.add_argument("--scan-sizes", type=int, nargs="+", default=[20, 22, 24],
+                    help="pass_scan: chain lengths")
+    ap.add_argument("--policy", default="auto", choices=["auto", "tile", "pipe"],
+                    help="pass_scan: kernel policy of the multi-vector passes (fq_set_kernel_policy)")
     ap.add_argument("--budget", type=float, default=400.0,
                     help="wall-clock budget in seconds of the default run: timed solves stop early so that the "
                          "comparison solve, the roofline passes and the JSON line fit in it")
     ap.add_argument("--scan-L", type=int, default=None,
                     help="(n_cv, k) scan of the brickwork circuit at this L (n_ev=50, z=1, complex128)")
-    ap.add_argument("--workload", default="ki_L20", choices=["ki_L20", "ki_batched", "bw_L24", "bw_paper", "nominal"],
+    ap.add_argument("--workload", default="ki_L20", choices=["ki_L20", "ki_batched", "bw_L24", "bw_paper", "nominal", "pass_scan"],
                     help="ki_batched: 256 realisations x 4 targets, L in 12..16, one batched call; "
                          "bw_L24: the brickwork filter (k=300) at L=24")
     ap.add_argument("--filter-steps", type=int, default=0,
@@ -588,6 +592,9 @@ def main():
     if args.workload == "nominal":
         nominal(args)
         return
+    if args.workload == "pass_scan":
+        pass_scan(args)
+        return
     from workloads import config_kicked_ising
     L = args.L
     k = args.k if args.k is not None else int(math.floor(0.8 * 2 ** (L + 1) / args.ncv))
@@ -737,6 +744,38 @@ def main():
         "wall_s": time.perf_counter() - t_start,
     }
     print(json.dumps(line), flush=True)
+
+
+def pass_scan(args):
+    """Horner pass of the kicked-Ising filter at L = 20, 22, 24 with 1, 2 and 4
+    vectors per launch, complex64 and complex128: average pass duration (HIP
+    events on the launch stream) and algorithmic GB/s (3 * n * d * s bytes
+    per pass).  One vector per launch is the single-vector filter; more
+    vectors go through apply_filter_many (autotuned tile shapes)."""
+    import torch
+
+    from paper_2102_05054_amd import kicked_ising
+    from paper_2102_05054_amd._lib import FQ_POLICY_AUTO, FQ_POLICY_PIPE, FQ_POLICY_TILE, lib
+    from workloads import config_kicked_ising
+    policy = {"auto": FQ_POLICY_AUTO, "tile": FQ_POLICY_TILE, "pipe": FQ_POLICY_PIPE}[args.policy]
+    assert lib().fq_set_kernel_policy(policy) == 0
+    rows = []
+    for L in args.scan_sizes:
+        q = config_kicked_ising("ki_L20", W=1.0, L=L)
+        with kicked_ising(q.L, q.J, q.h, q.g, q.periodic) as op:
+            for dt in ("c64", "c128"):
+                for n in (1, 2, 4):
+                    if n * (2 ** L) * (16 if dt == "c128" else 8) * 2 > (24 << 30):
+                        continue
+                    steps = max(50, min(2000, int(2e8 / (n * 2 ** L))))
+                    r = filter_roofline(op, L, steps, n, dt)
+                    row = {"L": L, "dtype": dt, "vectors": n, "policy": args.policy, "avg_pass_us": r["avg_launch_us"],
+                           "us_per_vector_pass": r["avg_launch_us"] / n, "alg_GBs": r["achieved_GBs"],
+                           "frac": r["achieved_GBs"] / 8000.0, "steps": steps}
+                    rows.append(row)
+                    print(json.dumps(row), flush=True)
+                    torch.cuda.empty_cache()
+    print(json.dumps({"pass_scan": rows}))
 
 
 def nominal(args):

@@ -30,8 +30,28 @@
 
 namespace fq {
 
+// One-qubit kicks on the register bits selected by mask.  In the direct form
+// every register bit is processed, with weight 0 (an exact identity) where
+// the mask is clear: straight-line code whose butterflies the compiler can
+// interleave, instead of one branch per bit, whose joins made it copy the
+// whole register array (measured: about as many moves as FMAs).
 template <typename Real, int RB, bool SW>
 __device__ __forceinline__ void kick_regs(cpx<Real> (&v)[1 << RB], unsigned mask, Real w) {
+  if constexpr (!SW) {
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      const Real wi = ((mask >> i) & 1u) ? w : Real(0);
+#pragma unroll
+      for (int m = 0; m < (1 << RB); ++m) {
+        if (m & (1 << i)) continue;
+        const int m2 = m | (1 << i);
+        const cpx<Real> a = v[m], b = v[m2];
+        v[m] = xpiwy(a, wi, b);
+        v[m2] = xpiwy(b, wi, a);
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < RB; ++i) {
     if (mask & (1u << i)) {
@@ -60,16 +80,18 @@ __device__ __forceinline__ void kick_regs(cpx<Real> (&v)[1 << RB], unsigned mask
 __device__ __forceinline__ unsigned lane_xor_u32(unsigned u, int lb) {
   const int x = static_cast<int>(u);
   switch (lb) {
+    // bound_ctrl set: every source lane of these patterns is valid, and the
+    // "old" operand is then never read, so no register is zeroed for it
     case 0:
-      return static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false));
+      return static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, true));
     case 1:
-      return static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false));
+      return static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, true));
     case 2: {
-      const int y = __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false);
-      return static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, y, 0x1B, 0xF, 0xF, false));
+      const int y = __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, true);
+      return static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, y, 0x1B, 0xF, 0xF, true));
     }
     case 3:
-      return static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false));
+      return static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, true));
     case 4: {
       const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
       return (threadIdx.x & 16u) ? r[0] : r[1];
@@ -89,9 +111,26 @@ __device__ __forceinline__ double lane_xor(double v, int lb) {
   return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
 }
 
-// mask: lane bits (0..5) to butterfly across the wavefront.
-template <typename Real, int RB, bool SW>
+// mask: lane bits (0..5) to butterfly across the wavefront; in the direct
+// form lane bits 0..NL-1 are processed with weight 0 where the mask is
+// clear (see kick_regs), NL being the number of lane bits the layout can
+// hold kicked bits in.
+template <typename Real, int RB, bool SW, int NL = 6>
 __device__ __forceinline__ void kick_lanes(cpx<Real> (&v)[1 << RB], unsigned mask, Real w) {
+  if constexpr (!SW) {
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      const Real wl = ((mask >> l) & 1u) ? w : Real(0);
+#pragma unroll
+      for (int m = 0; m < (1 << RB); ++m) {
+        cpx<Real> p;
+        p.x = lane_xor(v[m].x, l);
+        p.y = lane_xor(v[m].y, l);
+        v[m] = xpiwy(v[m], wl, p);
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int l = 0; l < 6; ++l) {
     if (mask & (1u << l)) {
@@ -107,6 +146,18 @@ __device__ __forceinline__ void kick_lanes(cpx<Real> (&v)[1 << RB], unsigned mas
       }
     }
   }
+}
+
+// lane bits that can carry kicked tile bits in layout A / layout B (see
+// masks_for): layout A only for tiles without register bits, layout B the
+// tile bits RB .. TB-1
+template <int RB, int TB>
+constexpr int lanes_a() {
+  return RB == 0 ? (TB < 6 ? TB : 6) : 0;
+}
+template <int RB, int TB>
+constexpr int lanes_b() {
+  return RB == 0 ? 0 : (TB - RB < 6 ? TB - RB : 6);
 }
 
 template <typename Real>
@@ -205,10 +256,10 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
     // part, the phase and the B part of the second kick, back in A the A
     // part of the second kick and chi (read in layout A)
     kick_regs<Real, RB, SW>(v, a.k1.regA, w);
-    kick_lanes<Real, RB, SW>(v, a.k1.laneA, w);
+    kick_lanes<Real, RB, SW, lanes_a<RB, TB>()>(v, a.k1.laneA, w);
     if (fold_b) a_to_b<Real, RB, TB>(v, lds, tid);
     kick_regs<Real, RB, SW>(v, a.k1.regB, w);
-    kick_lanes<Real, RB, SW>(v, a.k1.laneB, w);
+    kick_lanes<Real, RB, SW, lanes_b<RB, TB>()>(v, a.k1.laneB, w);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
       const int t = fold_b ? (tid << RB) + m : tid + (m << TB);
@@ -218,10 +269,10 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
         v[m] = cmul(v[m], ki_phase(tlo, thi, tm.g(t), a.m));
     }
     kick_regs<Real, RB, SW>(v, a.k2.regB, w);
-    kick_lanes<Real, RB, SW>(v, a.k2.laneB, w);
+    kick_lanes<Real, RB, SW, lanes_b<RB, TB>()>(v, a.k2.laneB, w);
     if (fold_b) b_to_a<Real, RB, TB>(v, lds, tid);
     kick_regs<Real, RB, SW>(v, a.k2.regA, w);
-    kick_lanes<Real, RB, SW>(v, a.k2.laneA, w);
+    kick_lanes<Real, RB, SW, lanes_a<RB, TB>()>(v, a.k2.laneA, w);
     const C pc = mk<Real>(static_cast<Real>(a.psi_coef_re), static_cast<Real>(a.psi_coef_im));
     const bool coef = (a.flags & KI_PSI_COEF) != 0;
 #pragma unroll
@@ -235,11 +286,11 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
   // rewrites only LDS slots it read itself (B slots in b_to_a, A slots in
   // the next a_to_b), so the barrier inside each layout change suffices.
   kick_regs<Real, RB, SW>(v, a.k1.regA, w);
-  kick_lanes<Real, RB, SW>(v, a.k1.laneA, w);
+  kick_lanes<Real, RB, SW, lanes_a<RB, TB>()>(v, a.k1.laneA, w);
   if (a.k1.regB | a.k1.laneB) {
     a_to_b<Real, RB, TB>(v, lds, tid);
     kick_regs<Real, RB, SW>(v, a.k1.regB, w);
-    kick_lanes<Real, RB, SW>(v, a.k1.laneB, w);
+    kick_lanes<Real, RB, SW, lanes_b<RB, TB>()>(v, a.k1.laneB, w);
     b_to_a<Real, RB, TB>(v, lds, tid);
   }
 
@@ -260,13 +311,15 @@ __global__ void __launch_bounds__(1 << TB) ki_pass_kernel(KiPassArgs<Real> a) {
   }
 
   // second kick (starts the next Horner step): layout A, then B, back to A
-  kick_regs<Real, RB, SW>(v, a.k2.regA, w);
-  kick_lanes<Real, RB, SW>(v, a.k2.laneA, w);
-  if (a.k2.regB | a.k2.laneB) {
-    a_to_b<Real, RB, TB>(v, lds, tid);
-    kick_regs<Real, RB, SW>(v, a.k2.regB, w);
-    kick_lanes<Real, RB, SW>(v, a.k2.laneB, w);
-    b_to_a<Real, RB, TB>(v, lds, tid);
+  if (a.k2.regA | a.k2.laneA | a.k2.regB | a.k2.laneB) {
+    kick_regs<Real, RB, SW>(v, a.k2.regA, w);
+    kick_lanes<Real, RB, SW, lanes_a<RB, TB>()>(v, a.k2.laneA, w);
+    if (a.k2.regB | a.k2.laneB) {
+      a_to_b<Real, RB, TB>(v, lds, tid);
+      kick_regs<Real, RB, SW>(v, a.k2.regB, w);
+      kick_lanes<Real, RB, SW, lanes_b<RB, TB>()>(v, a.k2.laneB, w);
+      b_to_a<Real, RB, TB>(v, lds, tid);
+    }
   }
 
 #pragma unroll
@@ -376,11 +429,11 @@ __global__ void __launch_bounds__(1 << TB)
 
     const Real w = cur.w;
     kick_regs<Real, RB, SW>(v, a.k1.regA, w);
-    kick_lanes<Real, RB, SW>(v, a.k1.laneA, w);
+    kick_lanes<Real, RB, SW, lanes_a<RB, TB>()>(v, a.k1.laneA, w);
     if (a.k1.regB | a.k1.laneB) {  // as in ki_pass_kernel: no barrier between layout changes
       a_to_b<Real, RB, TB>(v, lds, tid);
       kick_regs<Real, RB, SW>(v, a.k1.regB, w);
-      kick_lanes<Real, RB, SW>(v, a.k1.laneB, w);
+      kick_lanes<Real, RB, SW, lanes_b<RB, TB>()>(v, a.k1.laneB, w);
       b_to_a<Real, RB, TB>(v, lds, tid);
     }
     if (do_ph || do_ps) {
@@ -392,13 +445,15 @@ __global__ void __launch_bounds__(1 << TB)
         v[m] = x;
       }
     }
-    kick_regs<Real, RB, SW>(v, a.k2.regA, w);
-    kick_lanes<Real, RB, SW>(v, a.k2.laneA, w);
-    if (a.k2.regB | a.k2.laneB) {
-      a_to_b<Real, RB, TB>(v, lds, tid);
-      kick_regs<Real, RB, SW>(v, a.k2.regB, w);
-      kick_lanes<Real, RB, SW>(v, a.k2.laneB, w);
-      b_to_a<Real, RB, TB>(v, lds, tid);
+    if (a.k2.regA | a.k2.laneA | a.k2.regB | a.k2.laneB) {
+      kick_regs<Real, RB, SW>(v, a.k2.regA, w);
+      kick_lanes<Real, RB, SW, lanes_a<RB, TB>()>(v, a.k2.laneA, w);
+      if (a.k2.regB | a.k2.laneB) {
+        a_to_b<Real, RB, TB>(v, lds, tid);
+        kick_regs<Real, RB, SW>(v, a.k2.regB, w);
+        kick_lanes<Real, RB, SW, lanes_b<RB, TB>()>(v, a.k2.laneB, w);
+        b_to_a<Real, RB, TB>(v, lds, tid);
+      }
     }
 #pragma unroll
     for (int m = 0; m < R; ++m) gstore(cur.xout, cur.tm.g(tid + (m << TB)), v[m]);
@@ -475,16 +530,16 @@ __global__ void __launch_bounds__(1 << TB) ki_single_kernel(KiSingleArgs<Real> a
 
   for (int step = 0; step < a.steps; ++step) {
     kick_regs<Real, RB, SW>(v, a.kick.regB, w);
-    kick_lanes<Real, RB, SW>(v, a.kick.laneB, w);
+    kick_lanes<Real, RB, SW, lanes_b<RB, TB>()>(v, a.kick.laneB, w);
     if constexpr (RB > 0) {
       b_to_a<Real, RB, TB>(v, lds, tid);
       kick_regs<Real, RB, SW>(v, a.kick.regA, w);
-      kick_lanes<Real, RB, SW>(v, a.kick.laneA, w);
+      kick_lanes<Real, RB, SW, lanes_a<RB, TB>()>(v, a.kick.laneA, w);
       __syncthreads();
       a_to_b<Real, RB, TB>(v, lds, tid);
       __syncthreads();
     } else {
-      kick_lanes<Real, RB, SW>(v, a.kick.laneA, w);
+      kick_lanes<Real, RB, SW, lanes_a<RB, TB>()>(v, a.kick.laneA, w);
     }
     C coef = mk<Real>(1, 0);
     const bool use_coef = a.coefs != nullptr;
