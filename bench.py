@@ -783,8 +783,10 @@ def nominal(args):
     end (converged or not): L = 16 complex128, k = 200, nev = 50, ncv = 120,
     phi drawn, one vector per step; L = 20, k = 400, nev = 100, ncv = 220,
     W in {1, 3}, complex64 + FP64 refinement (block 4) and complex128
-    (block 2).  Each solve stops after --max-restarts restarts; status,
-    converged pairs and the largest FP64 residual are printed per solve."""
+    (block 2); the brickwork circuit at L = 24, k = 300, nev = 40, ncv = 100,
+    complex64 + FP64 (block 4, at most 3 restarts).  Each solve stops after
+    --max-restarts restarts; status, converged pairs and the largest FP64
+    residual are printed per solve."""
     import torch
 
     from paper_2102_05054_amd import kicked_ising
@@ -815,6 +817,25 @@ def nominal(args):
         p3 = config_kicked_ising("ki_L20", W=W)
         for dtype, block in (("c64", 4), ("c128", 2)):
             run(f"ki_L20 W={W:g} nominal", p3, c3["nev"], c3["ncv"], c3["k"], dtype, block, 0.0)
+    # the brickwork circuit at L = 24: three restart cycles at most (each
+    # cycle is ~3 s of filter, the first ~10 s), then one FP64 cycle
+    from paper_2102_05054_amd import brickwork
+    from workloads import brickwork as bw_params
+    c5 = CONFIGS["bw_L24"]
+    p5 = bw_params(c5["L"], c5["seed"])
+    with brickwork(p5.L, p5.gates) as op:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev, _, res, st, status = op.arnoldi_eigs(c5["nev"], 0.0, k=c5["k"], ncv=c5["ncv"], tol=c5["tol"],
+                                                 max_restarts=min(args.max_restarts, 3), filter_dtype="c64",
+                                                 seed=1, want_vectors=False, allow_not_converged=True, block=4)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    r = {"case": "bw_L24 nominal", "L": p5.L, "k": c5["k"], "nev": c5["nev"], "ncv": c5["ncv"], "dtype": "c64",
+         "block": 4, "status": int(status), "nconv": st["nconv"], "max_residual": float(res.max()),
+         "n_restarts": st["n_restarts"], "n_U_apps": st["n_U_apps"], "time_s": dt}
+    rows.append(r)
+    print(json.dumps(r), flush=True)
     print(json.dumps({"nominal": rows, "max_restarts": args.max_restarts}))
 
 

@@ -57,3 +57,31 @@ def test_brickwork_eigenstates_follow_page():
             page = entanglement.page(L, LA)
             say(f"L={L} LA={LA}: mean S {S.mean():.4f} +- {S.std():.4f}, Page {page:.4f}")
             assert abs(S.mean() - page) < 0.05
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("L", [16, 18])
+def test_circuit_workload_eigenstates_follow_page(L):
+    # The brickwork circuit workload's solve (nev = 40, ncv = 100, complex64
+    # filter + FP64 refinement, k by the paper's rule for this ncv) at sizes
+    # the oracle can check pair by pair: every residual recomputed with the
+    # oracle's matrix-free U, and the half-chain entropy of the eigenstates at
+    # Page's random-state value (Sec. 5, Eq. (page)).
+    from oracle import models
+    require_gpu()
+    p = brickwork(L, 5000 + L)
+    nev, ncv = 40, 100
+    with bw_op(p) as op:
+        ev, vecs, res, st, s = op.arnoldi_eigs(nev, 0.0, k=0, ncv=ncv, tol=1e-9, filter_dtype="c64", block=4, seed=2)
+        say(f"circuit workload L={L}: {st}")
+        assert s == 0 and res.max() <= 1e-9
+        S = op.entanglement_entropy(vecs, L // 2)
+        v = to_np(vecs)
+    r = [np.linalg.norm(models.bw_apply(p, v[n]) - ev[n] * v[n]) for n in range(nev)]
+    assert max(r) <= 1e-9
+    assert np.max(np.abs(np.abs(ev) - 1.0)) <= 1e-9
+    ref = [entanglement.entropy(v[n], L, L // 2) for n in range(0, nev, 8)]
+    assert np.allclose(S[0::8], ref, atol=1e-10)
+    page = entanglement.page(L, L // 2)
+    say(f"L={L} LA={L // 2}: mean S {S.mean():.4f} +- {S.std():.4f}, Page {page:.4f}")
+    assert abs(S.mean() - page) < 0.05
