@@ -159,6 +159,40 @@ KickMasks masks_for(unsigned kbits, int n, int rb, int tb) {
   return k;
 }
 
+// Each kicked bit goes to the first layout that holds it in a register (A:
+// bits tb..n-1, B: bits 0..3, C: bits S..S+3), bit 4 of a 13-bit tile to B's
+// lane 0.
+bool masks3_for(unsigned kbits, int n, int tb, KickMasks* ab, unsigned* c) {
+  if (tb < 6 || tb > 9 || n != 4 + tb) return false;
+  const int S = tb == 9 ? 5 : 4;
+  KickMasks k{0, 0, 0, 0};
+  unsigned cm = 0, done = 0;
+  auto take = [&](int q) { return ((kbits >> q) & 1u) && !((done >> q) & 1u); };
+  for (int q = tb; q < n; ++q)
+    if (take(q)) {
+      k.regA |= 1u << (q - tb);
+      done |= 1u << q;
+    }
+  for (int q = 0; q < 4; ++q)
+    if (take(q)) {
+      k.regB |= 1u << q;
+      done |= 1u << q;
+    }
+  if (S == 5 && take(4)) {
+    k.laneB |= 1u;
+    done |= 1u << 4;
+  }
+  for (int q = S; q < S + 4 && q < n; ++q)
+    if (take(q)) {
+      cm |= 1u << (q - S);
+      done |= 1u << q;
+    }
+  if (done != (kbits & ((1u << n) - 1u)) || (kbits >> n) != 0u) return false;
+  *ab = k;
+  *c = cm;
+  return true;
+}
+
 // Single-workgroup kernel: as many waves as the reachability rule allows.
 void single_shape(int L, int* rb, int* tb) {
   if (L <= 6) {
@@ -307,6 +341,22 @@ fq_status ki_pass(floquet_op* op, const KiGroup& gp, const PhaseTables* tab, con
   // few tiles per CU (latency-bound): fetch the phase entries with the tile;
   // complex128 only for the smallest states (register budget)
   if (gp.ntiles <= (sizeof(Real) == 4 ? 1024u : 512u)) a.flags |= KI_PREFETCH_PHASE;
+  // Horner passes of 16-amplitude tiles: the three-layout form
+  KickMasks m3;
+  unsigned c3 = 0;
+  if (!op->sw && gp.rb == 4 && (a.flags & ~KI_PREFETCH_PHASE) == (KI_PHASE | KI_ADD_PSI) &&
+      masks3_for(gp.kbits, gp.n, gp.tb, &m3, &c3)) {
+    a.k1 = m3;
+    a.k1c = c3;
+    a.k2 = k2 ? m3 : KickMasks{0, 0, 0, 0};
+    a.k2c = k2 ? c3 : 0u;
+    hipError_t e = ki_launch_pass3<Real>(a, gp.tb, gp.ntiles, s);
+    if (e != hipSuccess) {
+      set_error(std::string("kicked-Ising three-layout pass launch failed: ") + hipGetErrorString(e));
+      return FQ_EDEVICE;
+    }
+    return FQ_OK;
+  }
   a.k1 = masks_for(gp.kbits, gp.n, gp.rb, gp.tb);
   a.k2 = k2 ? a.k1 : KickMasks{0, 0, 0, 0};
   hipError_t e = ki_launch_pass<Real>(a, gp.rb, gp.tb, op->sw, gp.ntiles, s);

@@ -79,6 +79,18 @@ fq_status bpass(const KiBatchShape& sh, const KiGroup& g, const KiDesc<Real>* de
   a.flat = sh.flat ? 1 : 0;
   a.tile_log = 0;
   while ((1u << a.tile_log) < g.ntiles) ++a.tile_log;
+  KickMasks m3;
+  unsigned c3 = 0;
+  if (sh.three && !sh.sw && chi == 0 && g.rb == 4 && flags == (KI_PHASE | KI_ADD_PSI) && !from_psi &&
+      masks3_for(g.kbits, g.n, g.tb, &m3, &c3)) {
+    a.k1 = m3;
+    a.k1c = c3;
+    a.k2 = k2 ? m3 : KickMasks{0, 0, 0, 0};
+    a.k2c = k2 ? c3 : 0u;
+    const hipError_t e = ki_launch_pass3<Real>(a, g.tb, g.ntiles, s, n);
+    if (e != hipSuccess) return launch_err("batched three-layout kicked-Ising pass launch failed", e);
+    return FQ_OK;
+  }
   // the pipelined form has no folded variant
   if (sh.pipe > 0 && chi == 0 && pipe_shape(g.rb, g.tb, sizeof(Real) == 4)) {
     const size_t items = size_t(g.ntiles) * n;
@@ -162,6 +174,17 @@ std::vector<KiBatchShape> ki_batch_candidates(int L, bool sw, bool c64_dt) {
     c.plan = q;
     v.push_back(c);
   }
+  // the three-layout Horner passes for plans of 16-amplitude tiles only
+  if (!sw)
+    for (const KiPlan& q : plans) {
+      bool all4 = q.ngroups == 2;
+      for (int i = 0; i < q.ngroups; ++i) all4 = all4 && q.grp[i].rb == 4;
+      if (!all4) continue;
+      KiBatchShape c = base;
+      c.plan = q;
+      c.three = true;
+      v.push_back(c);
+    }
   return v;
 }
 
@@ -190,7 +213,7 @@ fq_status ki_batch_filter(const KiBatchShape& sh, int k, const KiDesc<Real>* des
   }
   fq_status st;
   if (pl.ngroups == 2) {
-    const bool fold = chi0 && chi1 && k >= 2;
+    const bool fold = chi0 && chi1 && k >= 2 && !sh.three;
     if (fold) {
       // chi_g = K_g psi for both groups
       st = bpass<Real>(sh, pl.grp[0], chi0, list, n, 1, 0, false, s);
@@ -406,10 +429,11 @@ fq_status ki_batch_tune(int L, bool sw, int k, const KiDesc<Real>* desc, const i
     return FQ_EDEVICE;
   }
   if (tune_verbose())
-    std::fprintf(stderr, "[fq] tuned L=%d %s n=%u k=%d: %s rb/tb %d/%d chunk %u flat %d prefetch %d pipe %u: %.2f us/step\n",
+    std::fprintf(stderr,
+                 "[fq] tuned L=%d %s n=%u k=%d: %s rb/tb %d/%d chunk %u flat %d prefetch %d pipe %u three %d: %.2f us/step\n",
                  L, c64_dt ? "c64" : "c128", n, k, best.single ? "single" : "multi-pass",
                  best.single ? best.srb : best.plan.grp[0].rb, best.single ? best.stb : best.plan.grp[0].tb,
-                 best.chunk, best.flat ? 1 : 0, best.prefetch, best.pipe, best_t);
+                 best.chunk, best.flat ? 1 : 0, best.prefetch, best.pipe, best.three ? 1 : 0, best_t);
   *out = best;
   if (best_us) *best_us = best_t;
   std::lock_guard<std::mutex> g(g_tune_mu);

@@ -30,6 +30,9 @@ struct KiBatchShape {
   // phase-table entries fetched with the tile (1), mid-pass (0), or by the
   // tile-count rule (-1): fetching early costs registers and occupancy
   int prefetch = -1;
+  // multi-pass only: Horner passes of 16-amplitude tiles in the three-layout
+  // form (ki_launch_pass3; no folded or pipelined variant)
+  bool three = false;
 };
 
 // Candidate shapes for (L, kick form, precision), the default first.

@@ -64,6 +64,9 @@ struct KiPassArgs {
   // kicks and the phase run between one A->B and one B->A change (two
   // layout changes per pass instead of four).  0: plain psi.
   int chi;
+  // three-layout passes (ki_launch_pass3): kicked register bits of layout C
+  // for the first / second kick (k1 / k2 carry layouts A and B and B's lane 0)
+  unsigned k1c, k2c;
 };
 
 template <typename Real>
@@ -98,6 +101,13 @@ hipError_t ki_launch_pass(const KiPassArgs<Real>& a, int rb, int tb, bool sw, un
 template <typename Real>
 hipError_t ki_launch_pipe(const KiPassArgs<Real>& a, int rb, int tb, bool sw, unsigned ntiles, unsigned nprob,
                           unsigned grid, hipStream_t s);
+// Horner pass (KI_PHASE | KI_ADD_PSI, no coefficients) over a tile of
+// n = 4 + tb bits in three register layouts, so that every kicked bit but at
+// most one (a DPP lane bit) is a register bit in one of them; complex64 only
+// (complex128 would need twice the registers).  nprob as in ki_launch_pass.
+template <typename Real>
+hipError_t ki_launch_pass3(const KiPassArgs<Real>& a, int tb, unsigned ntiles, hipStream_t s, unsigned nprob = 0);
+
 template <typename Real>
 hipError_t ki_launch_single(const KiSingleArgs<Real>& a, int rb, int tb, bool sw, bool psi_regs,
                             unsigned nblocks, hipStream_t s, bool batched = false);

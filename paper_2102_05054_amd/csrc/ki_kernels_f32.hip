@@ -7,6 +7,7 @@ namespace fq {
 
 template hipError_t ki_launch_pass<float>(const KiPassArgs<float>&, int, int, bool, unsigned, hipStream_t,
                                           unsigned);
+template hipError_t ki_launch_pass3<float>(const KiPassArgs<float>&, int, unsigned, hipStream_t, unsigned);
 template hipError_t ki_launch_pipe<float>(const KiPassArgs<float>&, int, int, bool, unsigned, unsigned, unsigned,
                                           hipStream_t);
 template hipError_t ki_launch_single<float>(const KiSingleArgs<float>&, int, int, bool, bool, unsigned,

@@ -572,6 +572,181 @@ __global__ void __launch_bounds__(1 << TB) ki_single_kernel(KiSingleArgs<Real> a
 }
 
 // ---------------------------------------------------------------------------
+// Horner pass in three register layouts (direct kick form, complex64).  A
+// workgroup of T = 2^TB threads holds a tile of n = 4 + TB bits, 16
+// amplitudes per thread, in one of
+//   A: j = t + T m                                   registers: bits TB .. n-1
+//   B: j = 16 t + m                                  registers: bits 0..3,
+//                                                    lane 0: bit 4
+//   C: j = (t mod 2^S) + 2^S m + 2^(S+4) (t >> S)    registers: bits S .. S+3
+// with S = 5 for TB = 9 (bit 4 then takes the one lane butterfly, a DPP xor 1
+// in B) and S = 4 otherwise.  Every other kicked bit is a register bit of one
+// layout: two FMAs per amplitude and bit, where the two-layout pass moves
+// five of thirteen bits across lanes.  Per pass: kick A, A->B, kick B, B->C,
+// kick C, phase and +psi in C (psi read in C order: 2^S consecutive tile
+// indices per group of lanes), kick C, C->B, kick B, B->A, kick A, store --
+// four layout changes, as in the two-layout pass.  The phase-table entries
+// are requested first and multiplied together while the tile is in flight.
+// ---------------------------------------------------------------------------
+template <int TB>
+constexpr int pass3_shift() {
+  return TB == 9 ? 5 : 4;
+}
+
+// Tile index of register 0 of thread t in layout L (0 = A, 1 = B, 2 = C);
+// register m sits pass3_step<TB, L>() tile indices further on.
+template <int TB, int L>
+__device__ __forceinline__ uint32_t pass3_index0(uint32_t t) {
+  constexpr int S = pass3_shift<TB>();
+  if constexpr (L == 0)
+    return t;
+  else if constexpr (L == 1)
+    return t << 4;
+  else
+    return (t & ((1u << S) - 1u)) + ((t >> S) << (S + 4));
+}
+template <int TB, int L>
+constexpr uint32_t pass3_step() {
+  return L == 0 ? (1u << TB) : (L == 1 ? 1u : (1u << pass3_shift<TB>()));
+}
+// LDS slot distance between consecutive registers (padding of lds_phys<4>:
+// steps of at least 16 tile indices gain one pad slot per 16)
+template <int TB, int L>
+constexpr uint32_t pass3_lds_step() {
+  return pass3_step<TB, L>() >= 16 ? pass3_step<TB, L>() + pass3_step<TB, L>() / 16 : pass3_step<TB, L>();
+}
+
+// Layout FROM -> TO through LDS.  A thread writes only the slots it read in
+// the previous change (its FROM slots), so one barrier per change suffices.
+template <typename Real, int TB, int FROM, int TO>
+__device__ __forceinline__ void relayout3(cpx<Real> (&v)[16], cpx<Real>* lds, uint32_t tid) {
+  cpx<Real>* w = lds + lds_phys<4>(pass3_index0<TB, FROM>(tid));
+  const cpx<Real>* r = lds + lds_phys<4>(pass3_index0<TB, TO>(tid));
+#pragma unroll
+  for (int m = 0; m < 16; ++m) w[m * pass3_lds_step<TB, FROM>()] = v[m];
+  lds_barrier();
+#pragma unroll
+  for (int m = 0; m < 16; ++m) v[m] = r[m * pass3_lds_step<TB, TO>()];
+}
+
+// Amplitude access with a uniform base and a 32-bit element offset (the
+// launcher admits states of at most 2^32 bytes): one offset register per
+// access instead of a 64-bit address.
+template <typename Real>
+__device__ __forceinline__ cpx<Real> gload32(const cpx<Real>* p, uint32_t i) {
+  using V = typename gvec2<Real>::type;
+  typedef const __attribute__((address_space(1))) char* GB;
+  typedef const __attribute__((address_space(1))) V* GP;
+  const V x = *(GP)((GB)p + i * uint32_t(sizeof(V)));  // C-style: address-space cast
+  return mk<Real>(x.x, x.y);
+}
+template <typename Real>
+__device__ __forceinline__ void gstore32(cpx<Real>* p, uint32_t i, cpx<Real> c) {
+  using V = typename gvec2<Real>::type;
+  typedef __attribute__((address_space(1))) char* GB;
+  typedef __attribute__((address_space(1))) V* GP;
+  V x;
+  x.x = c.x;
+  x.y = c.y;
+  *(GP)((GB)p + i * uint32_t(sizeof(V))) = x;
+}
+
+template <typename Real, int TB, int BATCH>
+__global__ void __launch_bounds__(1 << TB) ki_pass3_kernel(KiPassArgs<Real> a) {
+  using C = cpx<Real>;
+  constexpr int R = 16;
+  constexpr int S = pass3_shift<TB>();
+  extern __shared__ char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const uint32_t tid = threadIdx.x;
+  uint32_t tile;
+  const C* __restrict__ xin;
+  C* __restrict__ xout;
+  const C* __restrict__ psi;
+  const C* __restrict__ tlo;
+  const C* __restrict__ thi;
+  Real w;
+  if constexpr (BATCH != 0) {
+    uint32_t q;
+    if (a.flat) {
+      const uint32_t idx = xcd_tile(blockIdx.x, gridDim.x);
+      q = idx >> a.tile_log;
+      tile = idx & ((1u << a.tile_log) - 1u);
+    } else {
+      q = blockIdx.y;
+      tile = xcd_tile(blockIdx.x, gridDim.x);
+    }
+    const KiDesc<Real>& D = a.desc[a.list[q]];
+    xin = a.from_psi ? D.psi : D.x;
+    xout = D.x;
+    psi = D.psi;
+    tlo = D.tlo;
+    thi = D.thi;
+    w = static_cast<Real>(D.w);
+  } else {
+    tile = xcd_tile(blockIdx.x, gridDim.x);
+    xin = a.xin;
+    xout = a.xout;
+    psi = a.psi;
+    tlo = a.tlo;
+    thi = a.thi;
+    w = static_cast<Real>(a.w);
+  }
+  const TileMap tm = make_tile_map(tile, a.n, a.c, a.p);
+  const uint32_t mlo = (1u << a.m) - 1u;
+  // global index of register m of layouts A and C: g(index0) + m * stride
+  // (the register step is a power of two; below the chunk it stays in the
+  // chunk, above it moves the high part only)
+  const uint32_t cw = 1u << a.c;
+  const uint32_t stA = pass3_step<TB, 0>() < cw ? pass3_step<TB, 0>() : (pass3_step<TB, 0>() >> a.c) << a.p;
+  const uint32_t stC = pass3_step<TB, 2>() < cw ? pass3_step<TB, 2>() : (pass3_step<TB, 2>() >> a.c) << a.p;
+  const uint32_t gA = tm.g(pass3_index0<TB, 0>(tid));
+  const uint32_t gC = tm.g(pass3_index0<TB, 2>(tid));
+
+  // the tile in layout A, then the phase-table entries of the layout-C
+  // amplitudes (multiplied together once the first kick is done)
+  C tl[R], th[R], v[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) v[m] = gload32(xin, gA + uint32_t(m) * stA);
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    const uint32_t g = gC + uint32_t(m) * stC;
+    tl[m] = gload32(tlo, g & mlo);
+    th[m] = gload32(thi, ((g >> a.m) << 2) | ((g & 1u) << 1) | ((g >> (a.m - 1)) & 1u));
+  }
+
+  // first kick (finishes the Horner step begun by the previous pass)
+  kick_regs<Real, 4, false>(v, a.k1.regA, w);
+  C ph[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) ph[m] = cmul(tl[m], th[m]);
+  relayout3<Real, TB, 0, 1>(v, lds, tid);
+  C ps[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) ps[m] = gload32(psi, gC + uint32_t(m) * stC);
+  kick_regs<Real, 4, false>(v, a.k1.regB, w);
+  if constexpr (S == 5) kick_lanes<Real, 4, false, 1>(v, a.k1.laneB, w);
+  relayout3<Real, TB, 1, 2>(v, lds, tid);
+  kick_regs<Real, 4, false>(v, a.k1c, w);
+#pragma unroll
+  for (int m = 0; m < R; ++m) v[m] = cadd(cmul(v[m], ph[m]), ps[m]);
+
+  // second kick (starts the next step), or straight back to layout A
+  if (a.k2.regA | a.k2.regB | a.k2.laneB | a.k2c) {
+    kick_regs<Real, 4, false>(v, a.k2c, w);
+    relayout3<Real, TB, 2, 1>(v, lds, tid);
+    kick_regs<Real, 4, false>(v, a.k2.regB, w);
+    if constexpr (S == 5) kick_lanes<Real, 4, false, 1>(v, a.k2.laneB, w);
+    relayout3<Real, TB, 1, 0>(v, lds, tid);
+    kick_regs<Real, 4, false>(v, a.k2.regA, w);
+  } else {
+    relayout3<Real, TB, 2, 0>(v, lds, tid);
+  }
+#pragma unroll
+  for (int m = 0; m < R; ++m) gstore32(xout, gA + uint32_t(m) * stA, v[m]);
+}
+
+// ---------------------------------------------------------------------------
 // Host launchers: runtime (RB, TB, SW) -> template instance.
 // ---------------------------------------------------------------------------
 namespace {
@@ -580,6 +755,22 @@ template <typename Real, int RB, int TB, bool SW, bool PF, int BATCH>
 hipError_t launch_pass_t(const KiPassArgs<Real>& a, unsigned ntiles, unsigned nprob, hipStream_t s) {
   const size_t shmem = static_cast<size_t>(lds_slots<RB, TB>()) * sizeof(cpx<Real>);
   auto kern = ki_pass_kernel<Real, RB, TB, SW, PF, BATCH>;
+  static bool attr_set = false;
+  if (!attr_set && shmem > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const dim3 grid = BATCH == 0 ? dim3(ntiles) : (a.flat ? dim3(ntiles * nprob) : dim3(ntiles, nprob));
+  hipLaunchKernelGGL(kern, grid, dim3(1 << TB), shmem, s, a);
+  return hipGetLastError();
+}
+
+template <typename Real, int TB, int BATCH>
+hipError_t launch_pass3_t(const KiPassArgs<Real>& a, unsigned ntiles, unsigned nprob, hipStream_t s) {
+  const size_t shmem = static_cast<size_t>(lds_slots<4, TB>()) * sizeof(cpx<Real>);
+  auto kern = ki_pass3_kernel<Real, TB, BATCH>;
   static bool attr_set = false;
   if (!attr_set && shmem > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -668,6 +859,31 @@ hipError_t ki_launch_pass(const KiPassArgs<Real>& a, int rb, int tb, bool sw, un
 #undef FQ_CASE
 #undef FQ_CASE4
   return hipErrorInvalidValue;
+}
+
+template <typename Real>
+hipError_t ki_launch_pass3(const KiPassArgs<Real>& a, int tb, unsigned ntiles, hipStream_t s, unsigned nprob) {
+  {
+    // 32-bit byte offsets: at most 2^32 / sizeof(amplitude) amplitudes
+    // (register steps stay linear in the tile map: the chunk is the whole
+    // tile or at most 16 amplitudes)
+    if (a.n != 4 + tb || a.chi != 0 || (size_t(ntiles) << a.n) > ((size_t(1) << 32) / sizeof(cpx<Real>)) ||
+        (a.c != a.n && a.c > 4))
+      return hipErrorInvalidValue;
+    if (nprob > 0 && (!a.desc || !a.list || nprob > 65535u)) return hipErrorInvalidValue;
+    if (nprob > 0 && a.flat && (ntiles != (1u << a.tile_log) || size_t(ntiles) * nprob > 0x7fffffffu))
+      return hipErrorInvalidValue;
+#define FQ_CASE(TB_)                                                            \
+  if (tb == TB_)                                                                \
+    return nprob > 0 ? launch_pass3_t<Real, TB_, 1>(a, ntiles, nprob, s)        \
+                     : launch_pass3_t<Real, TB_, 0>(a, ntiles, 1, s);
+    FQ_CASE(6)
+    FQ_CASE(7)
+    FQ_CASE(8)
+    FQ_CASE(9)
+#undef FQ_CASE
+    return hipErrorInvalidValue;
+  }
 }
 
 // complex128 with 16 amplitudes per thread would spill (prefetched state,

@@ -44,6 +44,10 @@ struct BwProgram;
 void tile_shape(int n, int* rb, int* tb);
 void pass_shape(int n, unsigned ntiles, int* rb, int* tb);
 KickMasks masks_for(unsigned kbits, int n, int rb, int tb);
+// Kicked bits per layout of the three-layout pass (ki_launch_pass3, tiles of
+// n = 4 + tb bits): regA / regB / laneB (B's lane 0) in *ab, layout C's
+// register bits in *c.  false when the tile shape has no three-layout form.
+bool masks3_for(unsigned kbits, int n, int tb, KickMasks* ab, unsigned* c);
 void single_shape(int L, int* rb, int* tb);
 KiPlan make_plan(int L, bool c64_dt);
 bool single_ok(int L, bool c64_dt);
