@@ -120,7 +120,9 @@ def filter_roofline(op, L, steps, nvec=1, dtype="c64"):
     bytes_per_launch = nvec * 3 * esize * d
     real = "float" if dtype == "c64" else "double"
     return {
-        "kernel": f"ki_pass_kernel<{real},...> ({nvec} vector(s) per launch; Horner step: kick, phase, +psi, kick)",
+        "kernel": f"kicked-Ising Horner pass <{real}> ({nvec} vector(s) per launch: "
+                  f"{'ki_pass3_kernel / ki_pass_kernel, autotuned' if nvec > 1 else 'ki_pass3_kernel where the tile has 16 amplitudes per thread, else ki_pass_kernel'}; "
+                  f"kick, phase, +psi, kick)",
         "dtype": dtype,
         "vectors_per_launch": nvec,
         "avg_launch_us": avg_s * 1e6,
@@ -192,6 +194,9 @@ def traffic_per_pass(nvec, dtype, L=20):
         with open(traffic_file(nvec, L)) as f:
             rec = json.load(f)
         if rec.get("kernel_hash") == kernel_hash():
+            dom = rec.get(f"dominant_{dtype}")
+            if dom:
+                return dom["bytes_per_launch"]
             return rec.get(f"bytes_per_pass_{dtype}", rec["bytes_per_pass"] if dtype == "c64" else None)
     except (OSError, ValueError, KeyError):
         pass

@@ -62,22 +62,40 @@ def summarise(fetch_csv, write_csv, copy_bytes):
     w_factor = copy_bytes / (write[cname] * 1024.0)
     passes = {}
     for k in fetch:
-        if "ki_pass_kernel<float" in k or "ki_pass_kernel<double" in k:
+        if any(t in k for t in ("ki_pass_kernel<float", "ki_pass_kernel<double", "ki_pass3_kernel<float",
+                                "ki_pass3_kernel<double")):
             passes[k] = {
                 "fetch_bytes": fetch[k] * 1024.0 * f_factor,
                 "write_bytes": write.get(k, 0.0) * 1024.0 * w_factor,
                 "dispatches": nf[k],
             }
 
-    def per_pass(tag):
-        sel = [v for k, v in passes.items() if tag in k]
+    def per_pass(real):
+        sel = [v for k, v in passes.items() if f"_kernel<{real}" in k]
         n = sum(v["dispatches"] for v in sel)
         if n == 0:
             return None
         return sum((v["fetch_bytes"] + v["write_bytes"]) * v["dispatches"] for v in sel) / n
 
-    c64 = per_pass("ki_pass_kernel<float")
+    def dominant(real):
+        # the kernels of the tuned passes: those with at least half the
+        # dispatches of the most frequent one (the two tile groups of a plan
+        # alternate), dispatch-weighted
+        sel = {k: v for k, v in passes.items() if f"_kernel<{real}" in k}
+        if not sel:
+            return None
+        top = max(v["dispatches"] for v in sel.values())
+        main = {k: v for k, v in sel.items() if v["dispatches"] * 2 >= top}
+        n = sum(v["dispatches"] for v in main.values())
+        return {"kernels": sorted(main), "dispatches": n,
+                "bytes_per_launch": sum((v["fetch_bytes"] + v["write_bytes"]) * v["dispatches"]
+                                        for v in main.values()) / n}
+
+    c64 = per_pass("float")
     return {
+        # the kernel with the most dispatches (the tuned pass of the workload)
+        "dominant_c64": dominant("float"),
+        "dominant_c128": dominant("double"),
         "kernel_hash": kernel_hash(),
         "copy_kernel": cname,
         "calibration_factors": factors,
@@ -87,7 +105,7 @@ def summarise(fetch_csv, write_csv, copy_bytes):
         "per_kernel": passes,
         "bytes_per_pass": c64,
         "bytes_per_pass_c64": c64,
-        "bytes_per_pass_c128": per_pass("ki_pass_kernel<double"),
+        "bytes_per_pass_c128": per_pass("double"),
     }
 
 
