@@ -454,7 +454,7 @@ fq_status ritz(Bucket& B, const std::vector<int>& R) {
   FQ_TRY(B.upload(B.gemm, B.gemm_h, n * sizeof(GemmDesc)));
   FQ_TRY(B.upload(B.rd, B.rd_h, n * sizeof(RDesc)));
   FQ_TRY(B.upload(B.app, B.app_h, size_t(n) * nev * sizeof(KiDesc<double>)));
-  FQ_HIP_CHECK(launch_b_basis_gemm(B.gemm, n, B.d, B.s));
+  FQ_HIP_CHECK(launch_b_basis_gemm(B.gemm, n, B.d, B.s, nev));
   for (int i = 0; i < nev; ++i) {
     FQ_TRY(ki_batch_apply<double>(B.sh_app, B.app + size_t(i) * n, B.ident, n, B.s));
     FQ_HIP_CHECK(launch_r_rayleigh(B.rd, n, i, B.d, B.s));
@@ -497,7 +497,7 @@ fq_status restart(Bucket& B, const std::vector<int>& S) {
   FQ_TRY(B.upload(B.q, B.q_h, size_t(n) * B.ncv * B.qcols * sizeof(c128)));
   FQ_TRY(B.upload(B.gemm, B.gemm_h, n * sizeof(GemmDesc)));
   FQ_TRY(B.upload(B.aux, B.aux_h, n * sizeof(int)));
-  FQ_HIP_CHECK(launch_b_basis_gemm(B.gemm, n, B.d, B.s));
+  FQ_HIP_CHECK(launch_b_basis_gemm(B.gemm, n, B.d, B.s, p_keep));
   FQ_HIP_CHECK(launch_b_copy_col(B.args(B.aux, n), m, p_keep, B.s));
   for (int qi : S) {
     Prob& p = B.P[qi];
@@ -586,7 +586,7 @@ fq_status start_refine(Bucket& B, const std::vector<int>& W) {
   FQ_TRY(B.upload(B.q, B.q_h, size_t(n) * B.ncv * B.qcols * sizeof(c128)));
   FQ_TRY(B.upload(B.gemm, B.gemm_h, n * sizeof(GemmDesc)));
   FQ_TRY(B.upload(B.aux, B.aux_h, n * sizeof(int)));
-  FQ_HIP_CHECK(launch_b_basis_gemm(B.gemm, n, B.d, B.s));
+  FQ_HIP_CHECK(launch_b_basis_gemm(B.gemm, n, B.d, B.s, 1));
   FQ_HIP_CHECK(launch_b_normalize_col(B.args(B.aux, n), 0, B.s));
   for (int qi : W) {
     Prob& p = B.P[qi];

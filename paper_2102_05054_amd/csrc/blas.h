@@ -111,8 +111,9 @@ hipError_t launch_b_copy_col(const BatchArgs& a, int from, int to, hipStream_t s
 template <typename Real>
 hipError_t launch_b_cast_in(const BatchArgs& a, const KiDesc<Real>* fd, int j, hipStream_t s);
 hipError_t launch_b_cast_out(const BatchArgs& a, const KiDesc<float>* fd, hipStream_t s);
-// n basis products on the FP64 matrix cores (p <= 256, d a multiple of 16)
-hipError_t launch_b_basis_gemm(const GemmDesc* g, unsigned n, size_t d, hipStream_t s);
+// n basis products on the FP64 matrix cores (p <= pmax <= 256 in every
+// descriptor, d a multiple of 16; 64 rows per workgroup when d is a multiple of 64)
+hipError_t launch_b_basis_gemm(const GemmDesc* g, unsigned n, size_t d, hipStream_t s, int pmax);
 // Ritz pair i of n problems, after u = U y: omega, residual; y normalised
 hipError_t launch_r_rayleigh(const RDesc* rd, unsigned n, int i, size_t d, hipStream_t s);
 

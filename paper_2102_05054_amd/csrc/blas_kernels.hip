@@ -396,14 +396,14 @@ __global__ void __launch_bounds__(64) basis_gemm_mfma_kernel(const c128* __restr
 // tiles, fewer accumulator registers, more waves per SIMD.
 constexpr int kGemmKc = 8;
 template <int MAXT>
-__global__ void __launch_bounds__(256) basis_gemm_mfma64_kernel(const c128* __restrict__ V, size_t ldv, int m,
-                                                                const c128* __restrict__ Q, int p, c128* Y,
-                                                                size_t ldy) {
+__device__ __forceinline__ void basis_gemm_mfma64_body(const c128* __restrict__ V, size_t ldv, int m,
+                                                       const c128* __restrict__ Q, int p, c128* Y, size_t ldy,
+                                                       unsigned block) {
   extern __shared__ char gemm_smem[];
   c128* qs = reinterpret_cast<c128*>(gemm_smem);  // kGemmKc x p
   const int tid = threadIdx.x;
   const int l = tid & 63;
-  const size_t r0 = static_cast<size_t>(blockIdx.x) * 64 + 16 * (tid >> 6);
+  const size_t r0 = static_cast<size_t>(block) * 64 + 16 * (tid >> 6);
   const int ntile = (p + 15) >> 4;
   fq_d4 accr[MAXT], acci[MAXT];
 #pragma unroll
@@ -451,6 +451,13 @@ __global__ void __launch_bounds__(256) basis_gemm_mfma64_kernel(const c128* __re
       }
     }
   }
+}
+
+template <int MAXT>
+__global__ void __launch_bounds__(256) basis_gemm_mfma64_kernel(const c128* __restrict__ V, size_t ldv, int m,
+                                                                const c128* __restrict__ Q, int p, c128* Y,
+                                                                size_t ldy) {
+  basis_gemm_mfma64_body<MAXT>(V, ldv, m, Q, p, Y, ldy, blockIdx.x);
 }
 
 // Gram matrix G[i][j] = sum_t A(i,t) conj(A(j,t)), A(i,t) = X[i*si + t*st]
@@ -584,6 +591,13 @@ __global__ void b_cast_out_kernel(const KDesc* kd, const KiDesc<float>* fd, cons
 __global__ void __launch_bounds__(64) b_basis_gemm_kernel(const GemmDesc* g) {
   const GemmDesc& G = g[blockIdx.y];
   basis_gemm_mfma_body(G.V, G.ld, G.m, G.Q, G.p, G.Y, G.ld, blockIdx.x);
+}
+
+// the 64-row form of the single-problem rotation, one problem per blockIdx.y
+template <int MAXT>
+__global__ void __launch_bounds__(256) b_basis_gemm64_kernel(const GemmDesc* g) {
+  const GemmDesc& G = g[blockIdx.y];
+  basis_gemm_mfma64_body<MAXT>(G.V, G.ld, G.m, G.Q, G.p, G.Y, G.ld, blockIdx.x);
 }
 
 // Ritz pairs: y = Y[:, i] (not yet normalised), u = U y.
@@ -1003,8 +1017,23 @@ hipError_t launch_b_cast_out(const BatchArgs& a, const KiDesc<float>* fd, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_b_basis_gemm(const GemmDesc* g, unsigned n, size_t d, hipStream_t s) {
-  if (!g || n == 0 || n > 65535u || d % 16 != 0 || d < 16) return hipErrorInvalidValue;
+hipError_t launch_b_basis_gemm(const GemmDesc* g, unsigned n, size_t d, hipStream_t s, int pmax) {
+  if (!g || n == 0 || n > 65535u || d % 16 != 0 || d < 16 || pmax < 1 || pmax > 256) return hipErrorInvalidValue;
+  if (d % 64 == 0) {
+    // 64 rows per workgroup, Q staged in LDS (as launch_basis_gemm)
+    const size_t shmem = size_t(kGemmKc) * pmax * sizeof(c128);
+    const dim3 grid(static_cast<unsigned>(d / 64), n);
+    const int ntile = (pmax + 15) / 16;
+    if (ntile <= 4)
+      hipLaunchKernelGGL(b_basis_gemm64_kernel<4>, grid, dim3(256), shmem, s, g);
+    else if (ntile <= 8)
+      hipLaunchKernelGGL(b_basis_gemm64_kernel<8>, grid, dim3(256), shmem, s, g);
+    else if (ntile <= 12)
+      hipLaunchKernelGGL(b_basis_gemm64_kernel<12>, grid, dim3(256), shmem, s, g);
+    else
+      hipLaunchKernelGGL(b_basis_gemm64_kernel<16>, grid, dim3(256), shmem, s, g);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(b_basis_gemm_kernel, dim3(static_cast<unsigned>(d / 16), n), dim3(64), 0, s, g);
   return hipGetLastError();
 }
