@@ -83,7 +83,8 @@ def parse():
                          "matrix-core basis rotation")
     ap.add_argument("--profile-filter", action="store_true",
                     help="only the Horner filters (k=200, complex64 then complex128, --block vectors per launch) "
-                         "and the calibration copies, for counter runs")
+                         "and the calibration copies, for counter runs; with --workload bw_L24 or bw_paper "
+                         "--filter-steps, the calibration copies after that workload's filter")
     return ap.parse_args()
 
 
@@ -137,9 +138,7 @@ COPY_BYTES = 2 ** 30
 
 def profile_filter(op, L, nvec):
     """Workload of the counter runs: 200 Horner passes in complex64, then 200
-    in complex128, nvec vectors per launch, and two plain device copies of
-    COPY_BYTES (1 GiB, source evicted from L2 and the Infinity Cache by a
-    second 1 GiB write) that calibrate FETCH_SIZE / WRITE_SIZE in bytes."""
+    in complex128, nvec vectors per launch, and the calibration copies."""
     import torch
     for tdt in (torch.complex64, torch.complex128):
         psi = torch.randn((nvec, 2 ** L), dtype=tdt, device="cuda")
@@ -150,6 +149,16 @@ def profile_filter(op, L, nvec):
             op.apply_filter_many(psi, 200, 0.0, out=out)
         torch.cuda.synchronize()
         del psi, out
+    calibration_copies()
+    print(json.dumps({"profile_filter": True, "L": L, "vectors_per_launch": nvec, "copy_bytes": COPY_BYTES}))
+
+
+def calibration_copies():
+    """Two plain device copies of COPY_BYTES (1 GiB, source evicted from L2 and
+    the Infinity Cache by a second 1 GiB write) that calibrate FETCH_SIZE /
+    WRITE_SIZE in bytes."""
+    import torch
+    torch.cuda.synchronize()
     a = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda").fill_(1)
     c = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda").fill_(2)
     b = torch.empty_like(a)
@@ -157,8 +166,7 @@ def profile_filter(op, L, nvec):
     # second calibration copy through torch's elementwise kernel (float32 view)
     torch.mul(c.view(torch.float32), 1.0, out=a.view(torch.float32))
     torch.cuda.synchronize()
-    del c
-    print(json.dumps({"profile_filter": True, "L": L, "vectors_per_launch": nvec, "copy_bytes": COPY_BYTES}))
+    del a, b, c
 
 
 def profile_gemm(op, L, ncv, nev, block):
@@ -396,6 +404,8 @@ def brickwork_filter(args):
                      "TFLOPs": 32 * L * d / (us_step * 1e6), "filter_apps": steps, "ms": ms}
         del x, y
     op.close()
+    if args.profile_filter:
+        calibration_copies()
     c64 = out["c64"]
     line = {
         "metric": "U-applications/s and HBM GB/s of the brickwork filter at L=24",
@@ -495,6 +505,8 @@ def brickwork_block_filter(args, op, L):
         e1.record(s)
         s.synchronize()
     op.close()
+    if args.profile_filter:
+        calibration_copies()
     us_u = 1e3 * e0.elapsed_time(e1) / (k * b)
     tf = 32 * L * d / (us_u * 1e6)
     print(json.dumps({

@@ -159,12 +159,27 @@ KickMasks masks_for(unsigned kbits, int n, int rb, int tb) {
   return k;
 }
 
+int pass3_shift_host(int tb) { return tb == 10 ? 6 : (tb == 9 ? 5 : 4); }
+
+int table3_mode(int n, int tb, int c, int p, int m) {
+  if (tb < 6 || tb > 10 || n != 4 + tb || m < 2) return -1;
+  const int S = pass3_shift_host(tb);
+  bool lo = true, hi = true;
+  for (int j = S; j < S + 4; ++j) {
+    const int gb = j < c ? j : p + (j - c);  // global bit of tile bit j
+    if (gb >= m) lo = false;
+    if (gb < m) hi = false;
+    if (gb == 0 || gb == m - 1) lo = false;
+  }
+  return lo ? 0 : (hi ? 1 : -1);
+}
+
 // Each kicked bit goes to the first layout that holds it in a register (A:
-// bits tb..n-1, B: bits 0..3, C: bits S..S+3), bit 4 of a 13-bit tile to B's
-// lane 0.
+// bits tb..n-1, B: bits 0..3, C: bits S..S+3); bits 4 .. S-1 (bit 4 of a
+// 13-bit tile, bits 4 and 5 of a 14-bit tile) to B's lanes 0 .. S-5.
 bool masks3_for(unsigned kbits, int n, int tb, KickMasks* ab, unsigned* c) {
-  if (tb < 6 || tb > 9 || n != 4 + tb) return false;
-  const int S = tb == 9 ? 5 : 4;
+  if (tb < 6 || tb > 10 || n != 4 + tb) return false;
+  const int S = pass3_shift_host(tb);
   KickMasks k{0, 0, 0, 0};
   unsigned cm = 0, done = 0;
   auto take = [&](int q) { return ((kbits >> q) & 1u) && !((done >> q) & 1u); };
@@ -178,10 +193,11 @@ bool masks3_for(unsigned kbits, int n, int tb, KickMasks* ab, unsigned* c) {
       k.regB |= 1u << q;
       done |= 1u << q;
     }
-  if (S == 5 && take(4)) {
-    k.laneB |= 1u;
-    done |= 1u << 4;
-  }
+  for (int q = 4; q < S; ++q)
+    if (take(q)) {
+      k.laneB |= 1u << (q - 4);
+      done |= 1u << q;
+    }
   for (int q = S; q < S + 4 && q < n; ++q)
     if (take(q)) {
       cm |= 1u << (q - S);
@@ -206,13 +222,38 @@ void single_shape(int L, int* rb, int* tb) {
   *rb = L - t;
 }
 
-KiPlan make_plan(int L, bool c64_dt) {
+KiPlan make_plan(int L, bool c64_dt, bool wide) {
   KiPlan pl;
   // chunk of contiguous amplitudes in the high-bit tiles: 64 bytes, or 32
-  // bytes when that keeps both tiles at <= 13 bits (<= 512 threads)
-  int c = c64_dt ? 3 : 2;
-  if (c64_dt && L + 3 > 26 && L + 2 <= 26) c = 2;
+  // bytes when that keeps both tiles at <= 13 bits (<= 512 threads).  With
+  // wide (complex64 in the direct kick form), a low-bit tile of 14 bits
+  // (the three-layout pass with 1024 threads and 136 KiB of LDS) keeps the
+  // 64-byte chunk where 13 bits would need a 32-byte one (L = 24); the
+  // high-bit tile stays at <= 13 bits, since its kick-only passes run in the
+  // other pass kernel
   const int nmax = 13;
+  int c = c64_dt ? 3 : 2;
+  if (c64_dt && wide && L + 3 == 2 * nmax + 1) {
+    const int nlo = nmax + 1, nhi = L + 3 - nlo;
+    pl.ngroups = 2;
+    KiGroup& lo = pl.grp[0];
+    lo.n = nlo;
+    lo.c = nlo;
+    lo.p = nlo;
+    lo.kbits = (1u << nlo) - 1u;
+    lo.ntiles = 1u << (L - nlo);
+    lo.rb = 4;
+    lo.tb = nlo - 4;
+    KiGroup& hi = pl.grp[1];
+    hi.n = nhi;
+    hi.c = 3;
+    hi.p = nlo;
+    hi.kbits = ((1u << nhi) - 1u) & ~7u;
+    hi.ntiles = 1u << (L - nhi);
+    pass_shape(hi.n, hi.ntiles, &hi.rb, &hi.tb);
+    return pl;
+  }
+  if (c64_dt && L + 3 > 2 * nmax && L + 2 <= 2 * nmax) c = 2;
   if (L + c <= 2 * nmax) {
     const int tot = L + c;
     const int nlo = (tot + 1) / 2;
@@ -315,7 +356,8 @@ template <typename Real>
 fq_status ki_pass(floquet_op* op, const KiGroup& gp, const PhaseTables* tab, const void* xin, void* xout,
                   const void* psi, int flags, bool k2, zd psi_coef, zd in_coef, hipStream_t s) {
   // a tile must cover every thread of the workgroup and stay inside the state
-  if (gp.n < gp.tb || gp.rb + gp.tb != gp.n || gp.rb > 4 || gp.tb > 9 || gp.tb > gp.rb + 6 || gp.n > op->L ||
+  // (1024-thread tiles: complex64 three-layout passes only, checked below)
+  if (gp.n < gp.tb || gp.rb + gp.tb != gp.n || gp.rb > 4 || gp.tb > 10 || gp.tb > gp.rb + 6 || gp.n > op->L ||
       (size_t(gp.ntiles) << gp.n) != op->dim()) {
     set_error("internal: inconsistent kicked-Ising tile plan");
     return FQ_EINVAL;
@@ -341,13 +383,14 @@ fq_status ki_pass(floquet_op* op, const KiGroup& gp, const PhaseTables* tab, con
   // few tiles per CU (latency-bound): fetch the phase entries with the tile;
   // complex128 only for the smallest states (register budget)
   if (gp.ntiles <= (sizeof(Real) == 4 ? 1024u : 512u)) a.flags |= KI_PREFETCH_PHASE;
-  // Horner passes of 16-amplitude tiles: the three-layout form
+  // passes with the phase over 16-amplitude tiles: the three-layout form
   KickMasks m3;
   unsigned c3 = 0;
-  if (!op->sw && gp.rb == 4 && (a.flags & ~KI_PREFETCH_PHASE) == (KI_PHASE | KI_ADD_PSI) &&
-      masks3_for(gp.kbits, gp.n, gp.tb, &m3, &c3)) {
+  const int t3 = table3_mode(gp.n, gp.tb, gp.c, gp.p, op->m);
+  if (!op->sw && gp.rb == 4 && pass3_flags_ok(a.flags) && t3 >= 0 && masks3_for(gp.kbits, gp.n, gp.tb, &m3, &c3)) {
     a.k1 = m3;
     a.k1c = c3;
+    a.t3 = t3;
     a.k2 = k2 ? m3 : KickMasks{0, 0, 0, 0};
     a.k2c = k2 ? c3 : 0u;
     hipError_t e = ki_launch_pass3<Real>(a, gp.tb, gp.ntiles, s);
@@ -356,6 +399,10 @@ fq_status ki_pass(floquet_op* op, const KiGroup& gp, const PhaseTables* tab, con
       return FQ_EDEVICE;
     }
     return FQ_OK;
+  }
+  if (gp.tb > 9) {
+    set_error("internal: a 1024-thread kicked-Ising tile needs the three-layout pass");
+    return FQ_EINVAL;
   }
   a.k1 = masks_for(gp.kbits, gp.n, gp.rb, gp.tb);
   a.k2 = k2 ? a.k1 : KickMasks{0, 0, 0, 0};
@@ -583,8 +630,8 @@ fq_status create_floquet_op(const fq_model_desc* desc, floquet_op** out) {
       op->site_scale = zd(0.0, -sn);
     }
     op->m = (op->L + 1) / 2;
-    op->plan64 = make_plan(op->L, true);
-    op->plan128 = make_plan(op->L, false);
+    op->plan64 = make_plan(op->L, true, !op->sw);
+    op->plan128 = make_plan(op->L, false, false);
     const PhaseTables* t;
     fq_status st = get_tables(op.get(), 0.0, &t);
     if (st != FQ_OK) return st;

@@ -32,15 +32,18 @@ bool pipe_shape(int rb, int tb, bool c64_dt) {
   return false;
 }
 
-bool group_ok(const KiGroup& g, size_t d) {
-  return g.n >= g.tb && g.rb >= 0 && g.rb + g.tb == g.n && g.rb <= 4 && g.tb <= 9 && g.tb <= g.rb + 6 &&
-         (size_t(g.ntiles) << g.n) == d && shape_compiled(g.rb, g.tb);
+// three: the plan runs its phase passes in the three-layout form, which
+// also has 14-bit (1024-thread) tiles
+bool group_ok(const KiGroup& g, size_t d, bool three) {
+  const bool wide = three && g.rb == 4 && g.tb == 10;
+  return g.n >= g.tb && g.rb >= 0 && g.rb + g.tb == g.n && g.rb <= 4 && g.tb <= (wide ? 10 : 9) &&
+         g.tb <= g.rb + 6 && (size_t(g.ntiles) << g.n) == d && (wide || shape_compiled(g.rb, g.tb));
 }
 
-bool plan_ok(const KiPlan& p, int L) {
+bool plan_ok(const KiPlan& p, int L, bool three = false) {
   if (p.ngroups < 2) return false;
   for (int i = 0; i < p.ngroups; ++i)
-    if (!group_ok(p.grp[i], size_t(1) << L)) return false;
+    if (!group_ok(p.grp[i], size_t(1) << L, three)) return false;
   return true;
 }
 
@@ -81,10 +84,12 @@ fq_status bpass(const KiBatchShape& sh, const KiGroup& g, const KiDesc<Real>* de
   while ((1u << a.tile_log) < g.ntiles) ++a.tile_log;
   KickMasks m3;
   unsigned c3 = 0;
-  if (sh.three && !sh.sw && chi == 0 && g.rb == 4 && flags == (KI_PHASE | KI_ADD_PSI) && !from_psi &&
+  const int t3 = table3_mode(g.n, g.tb, g.c, g.p, a.m);
+  if (sh.three && !sh.sw && chi == 0 && g.rb == 4 && pass3_flags_ok(a.flags) && !from_psi && t3 >= 0 &&
       masks3_for(g.kbits, g.n, g.tb, &m3, &c3)) {
     a.k1 = m3;
     a.k1c = c3;
+    a.t3 = t3;
     a.k2 = k2 ? m3 : KickMasks{0, 0, 0, 0};
     a.k2c = k2 ? c3 : 0u;
     const hipError_t e = ki_launch_pass3<Real>(a, g.tb, g.ntiles, s, n);
@@ -151,7 +156,7 @@ std::vector<KiBatchShape> ki_batch_candidates(int L, bool sw, bool c64_dt) {
       v.push_back(c);
     }
   }
-  const KiPlan pl = make_plan(L, c64_dt);
+  const KiPlan pl = make_plan(L, c64_dt, false);
   std::vector<KiPlan> plans;
   if (plan_ok(pl, L)) plans.push_back(pl);
   for (int rbv : {4, 3, 2}) {
@@ -174,9 +179,15 @@ std::vector<KiBatchShape> ki_batch_candidates(int L, bool sw, bool c64_dt) {
     c.plan = q;
     v.push_back(c);
   }
-  // the three-layout Horner passes for plans of 16-amplitude tiles only
-  if (!sw)
-    for (const KiPlan& q : plans) {
+  // the three-layout Horner passes for plans of 16-amplitude tiles only,
+  // with the 14-bit complex64 tiles where they apply
+  if (!sw) {
+    std::vector<KiPlan> plans3 = plans;
+    const KiPlan wide = make_plan(L, c64_dt, c64_dt);
+    bool dup = false;
+    for (const KiPlan& o : plans3) dup = dup || (same_plan(o, wide) && o.grp[0].n == wide.grp[0].n);
+    if (!dup && plan_ok(wide, L, true)) plans3.push_back(wide);
+    for (const KiPlan& q : plans3) {
       bool all4 = q.ngroups == 2;
       for (int i = 0; i < q.ngroups; ++i) all4 = all4 && q.grp[i].rb == 4;
       if (!all4) continue;
@@ -185,6 +196,7 @@ std::vector<KiBatchShape> ki_batch_candidates(int L, bool sw, bool c64_dt) {
       c.three = true;
       v.push_back(c);
     }
+  }
   return v;
 }
 
@@ -207,7 +219,7 @@ fq_status ki_batch_filter(const KiBatchShape& sh, int k, const KiDesc<Real>* des
     return FQ_OK;
   }
   const KiPlan& pl = sh.plan;
-  if (!plan_ok(pl, sh.L)) {
+  if (!plan_ok(pl, sh.L, sh.three)) {
     set_error("internal: inconsistent batched kicked-Ising tile plan");
     return FQ_EINVAL;
   }
@@ -249,7 +261,7 @@ fq_status ki_batch_apply(const KiBatchShape& sh, const KiDesc<Real>* desc, const
   if (n == 0) return FQ_OK;
   if (sh.single) return bsingle<Real>(sh, desc, list, n, 1, 0, s);
   const KiPlan& pl = sh.plan;
-  if (!plan_ok(pl, sh.L)) {
+  if (!plan_ok(pl, sh.L, sh.three)) {
     set_error("internal: inconsistent batched kicked-Ising tile plan");
     return FQ_EINVAL;
   }
@@ -313,8 +325,9 @@ fq_status ki_batch_shape_untimed(int L, bool sw, int k, unsigned n, KiBatchShape
       return FQ_OK;
     }
   }
-  c.plan = make_plan(L, c64_dt);
-  if (!plan_ok(c.plan, L)) {
+  c.plan = make_plan(L, c64_dt, c64_dt && !sw);
+  for (int i = 0; i < c.plan.ngroups; ++i) c.three = c.three || c.plan.grp[i].tb > 9;
+  if (!plan_ok(c.plan, L, c.three)) {
     set_error("no kicked-Ising tile shape for L = " + std::to_string(L));
     return FQ_EINVAL;
   }

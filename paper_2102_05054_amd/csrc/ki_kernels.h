@@ -65,8 +65,11 @@ struct KiPassArgs {
   // layout changes per pass instead of four).  0: plain psi.
   int chi;
   // three-layout passes (ki_launch_pass3): kicked register bits of layout C
-  // for the first / second kick (k1 / k2 carry layouts A and B and B's lane 0)
+  // for the first / second kick (k1 / k2 carry layouts A and B and B's lane 0),
+  // and the phase table that varies over layout C's registers (0: the low
+  // table, one high-table entry per thread; 1: the high table, one low entry)
   unsigned k1c, k2c;
+  int t3;
 };
 
 template <typename Real>

@@ -572,25 +572,28 @@ __global__ void __launch_bounds__(1 << TB) ki_single_kernel(KiSingleArgs<Real> a
 }
 
 // ---------------------------------------------------------------------------
-// Horner pass in three register layouts (direct kick form, complex64).  A
-// workgroup of T = 2^TB threads holds a tile of n = 4 + TB bits, 16
-// amplitudes per thread, in one of
+// Horner pass in three register layouts (direct kick form).  A workgroup of
+// T = 2^TB threads holds a tile of n = 4 + TB bits, 16 amplitudes per
+// thread, in one of
 //   A: j = t + T m                                   registers: bits TB .. n-1
 //   B: j = 16 t + m                                  registers: bits 0..3,
-//                                                    lane 0: bit 4
+//                                                    lanes 0..S-5: bits 4..S-1
 //   C: j = (t mod 2^S) + 2^S m + 2^(S+4) (t >> S)    registers: bits S .. S+3
-// with S = 5 for TB = 9 (bit 4 then takes the one lane butterfly, a DPP xor 1
-// in B) and S = 4 otherwise.  Every other kicked bit is a register bit of one
-// layout: two FMAs per amplitude and bit, where the two-layout pass moves
+// with S = 4 for TB <= 8, 5 for TB = 9 (bit 4 takes a DPP xor 1 in B) and 6
+// for TB = 10 (bits 4 and 5: DPP xor 1 and xor 2 in B; complex64 only, the
+// tile fills 136 KiB of LDS).  Every other kicked bit is a register bit of
+// one layout: two FMAs per amplitude and bit, where the two-layout pass moves
 // five of thirteen bits across lanes.  Per pass: kick A, A->B, kick B, B->C,
 // kick C, phase and +psi in C (psi read in C order: 2^S consecutive tile
 // indices per group of lanes), kick C, C->B, kick B, B->A, kick A, store --
 // four layout changes, as in the two-layout pass.  The phase-table entries
 // are requested first and multiplied together while the tile is in flight.
+// Flags: KI_PHASE always; KI_ADD_PSI optional (with KI_PSI_COEF: + c psi);
+// no second kick and no psi for the last pass of a U application.
 // ---------------------------------------------------------------------------
 template <int TB>
 constexpr int pass3_shift() {
-  return TB == 9 ? 5 : 4;
+  return TB == 10 ? 6 : (TB == 9 ? 5 : 4);
 }
 
 // Tile index of register 0 of thread t in layout L (0 = A, 1 = B, 2 = C);
@@ -704,46 +707,70 @@ __global__ void __launch_bounds__(1 << TB) ki_pass3_kernel(KiPassArgs<Real> a) {
   const uint32_t gC = tm.g(pass3_index0<TB, 2>(tid));
 
   // the tile in layout A, then the phase-table entries of the layout-C
-  // amplitudes (multiplied together once the first kick is done)
-  C tl[R], th[R], v[R];
+  // amplitudes (multiplied together once the first kick is done).  Layout C's
+  // register bits lie all below the table split (t3 = 0: the low-table index
+  // steps with the register, the high-table entry is the thread's) or all
+  // above it (t3 = 1: the other way round); no register bit is a boundary
+  // bit of the split, and register 0's index has them clear, so the varying
+  // index is base + m * step.
+  C tv[R], v[R];
 #pragma unroll
   for (int m = 0; m < R; ++m) v[m] = gload32(xin, gA + uint32_t(m) * stA);
+  const uint32_t ilo = gC & mlo;
+  const uint32_t ihi = ((gC >> a.m) << 2) | ((gC & 1u) << 1) | ((gC >> (a.m - 1)) & 1u);
+  const C* __restrict__ tvar = a.t3 ? thi : tlo;
+  const uint32_t ivar = a.t3 ? ihi : ilo;
+  const uint32_t svar = a.t3 ? (stC >> a.m) << 2 : stC;
 #pragma unroll
-  for (int m = 0; m < R; ++m) {
-    const uint32_t g = gC + uint32_t(m) * stC;
-    tl[m] = gload32(tlo, g & mlo);
-    th[m] = gload32(thi, ((g >> a.m) << 2) | ((g & 1u) << 1) | ((g >> (a.m - 1)) & 1u));
-  }
+  for (int m = 0; m < R; ++m) tv[m] = gload32(tvar, ivar + uint32_t(m) * svar);
+  const C tc = a.t3 ? gload32(tlo, ilo) : gload32(thi, ihi);
 
   // first kick (finishes the Horner step begun by the previous pass)
   kick_regs<Real, 4, false>(v, a.k1.regA, w);
   C ph[R];
 #pragma unroll
-  for (int m = 0; m < R; ++m) ph[m] = cmul(tl[m], th[m]);
+  for (int m = 0; m < R; ++m) ph[m] = cmul(tv[m], tc);
   relayout3<Real, TB, 0, 1>(v, lds, tid);
+  // without psi, the input stands in for it with coefficient 0 (finite
+  // values, so the product vanishes)
+  const bool add_psi = (a.flags & KI_ADD_PSI) != 0;
+  const bool coef = !add_psi || (a.flags & KI_PSI_COEF) != 0;
+  const C pc = add_psi ? mk<Real>(static_cast<Real>(a.psi_coef_re), static_cast<Real>(a.psi_coef_im))
+                       : mk<Real>(Real(0), Real(0));
+  const C* __restrict__ pin = add_psi ? psi : xin;
   C ps[R];
 #pragma unroll
-  for (int m = 0; m < R; ++m) ps[m] = gload32(psi, gC + uint32_t(m) * stC);
+  for (int m = 0; m < R; ++m) ps[m] = gload32(pin, gC + uint32_t(m) * stC);
   kick_regs<Real, 4, false>(v, a.k1.regB, w);
-  if constexpr (S == 5) kick_lanes<Real, 4, false, 1>(v, a.k1.laneB, w);
+  if constexpr (S > 4) kick_lanes<Real, 4, false, S - 4>(v, a.k1.laneB, w);
   relayout3<Real, TB, 1, 2>(v, lds, tid);
   kick_regs<Real, 4, false>(v, a.k1c, w);
+  if (coef) {
 #pragma unroll
-  for (int m = 0; m < R; ++m) v[m] = cadd(cmul(v[m], ph[m]), ps[m]);
+    for (int m = 0; m < R; ++m) v[m] = cfma(ps[m], pc, cmul(v[m], ph[m]));
+  } else {
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = cadd(cmul(v[m], ph[m]), ps[m]);
+  }
 
   // second kick (starts the next step), or straight back to layout A
   if (a.k2.regA | a.k2.regB | a.k2.laneB | a.k2c) {
     kick_regs<Real, 4, false>(v, a.k2c, w);
     relayout3<Real, TB, 2, 1>(v, lds, tid);
     kick_regs<Real, 4, false>(v, a.k2.regB, w);
-    if constexpr (S == 5) kick_lanes<Real, 4, false, 1>(v, a.k2.laneB, w);
+    if constexpr (S > 4) kick_lanes<Real, 4, false, S - 4>(v, a.k2.laneB, w);
     relayout3<Real, TB, 1, 0>(v, lds, tid);
     kick_regs<Real, 4, false>(v, a.k2.regA, w);
   } else {
     relayout3<Real, TB, 2, 0>(v, lds, tid);
   }
+  // the store offsets are recomputed from an opaque copy of the tile base:
+  // otherwise the compiler keeps the sixteen load offsets live (as 64-bit
+  // addresses) across the whole pass
+  uint32_t gS = gA;
+  asm volatile("" : "+v"(gS));
 #pragma unroll
-  for (int m = 0; m < R; ++m) gstore32(xout, gA + uint32_t(m) * stA, v[m]);
+  for (int m = 0; m < R; ++m) gstore32(xout, gS + uint32_t(m) * stA, v[m]);
 }
 
 // ---------------------------------------------------------------------------
@@ -881,6 +908,9 @@ hipError_t ki_launch_pass3(const KiPassArgs<Real>& a, int tb, unsigned ntiles, h
     FQ_CASE(7)
     FQ_CASE(8)
     FQ_CASE(9)
+    if constexpr (sizeof(Real) == 4) {
+      FQ_CASE(10)
+    }
 #undef FQ_CASE
     return hipErrorInvalidValue;
   }

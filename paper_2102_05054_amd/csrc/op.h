@@ -48,8 +48,22 @@ KickMasks masks_for(unsigned kbits, int n, int rb, int tb);
 // n = 4 + tb bits): regA / regB / laneB (B's lane 0) in *ab, layout C's
 // register bits in *c.  false when the tile shape has no three-layout form.
 bool masks3_for(unsigned kbits, int n, int tb, KickMasks* ab, unsigned* c);
+// Phase-table access of the three-layout pass for a tile map (n tile bits,
+// chunk c, high run at p) and table split m: 0 when layout C's register bits
+// are all below the split and off its two boundary bits (bits 0 and m - 1),
+// so that each thread needs one high-table entry; 1 when they are all at or
+// above the split (one low-table entry); -1 otherwise (no three-layout form).
+int table3_mode(int n, int tb, int c, int p, int m);
 void single_shape(int L, int* rb, int* tb);
-KiPlan make_plan(int L, bool c64_dt);
+// Tile plan of a chain of L sites; wide admits the 14-bit complex64 tiles of
+// the three-layout pass (direct kick form only).
+KiPlan make_plan(int L, bool c64_dt, bool wide);
+// Flags the three-layout pass takes: the phase, optionally + psi (with a
+// coefficient); not the input scale of the first pass.
+inline bool pass3_flags_ok(int flags) {
+  return (flags & ~(KI_PREFETCH_PHASE | KI_ADD_PSI | KI_PSI_COEF)) == KI_PHASE;
+}
+int pass3_shift_host(int tb);
 bool single_ok(int L, bool c64_dt);
 
 }  // namespace fq

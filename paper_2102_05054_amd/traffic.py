@@ -1,15 +1,18 @@
-"""HBM traffic of the Horner pass kernel from rocprofv3 counter runs.
+"""HBM traffic of the filter pass kernels from rocprofv3 counter runs.
 
-rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) over ``bench.py --profile-filter``
-reports KiB per dispatch for the pass kernels and for a plain device copy of
-known size (the calibration: the copy moves exactly ``copy_bytes`` each way).
-``summarise`` turns the two counter CSVs into bytes per pass launch (complex64
-and complex128 passes separately), scaled by the copy's known / measured
-ratio, and records the hash of the kernel source so that a stale measurement
-is never reported for a changed kernel.
+rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) over a ``bench.py
+--profile-filter`` run reports KiB per dispatch for the pass kernels and for a
+plain device copy of known size (the calibration: the copy moves exactly
+``copy_bytes`` each way).  ``summarise`` turns the two counter CSVs into bytes
+per pass launch (complex64 and complex128 passes separately), scaled by the
+copy's known / measured ratio, and records the hash of the kernel source so
+that a stale measurement is never reported for a changed kernel.  Family
+``ki`` is the kicked-Ising Horner pass (one launch per Horner step), family
+``bw`` the brickwork passes (two launches per Horner step: right block, then
+left block with +psi).
 
 Usage:
-  python -m paper_2102_05054_amd.traffic FETCH.csv WRITE.csv COPY_BYTES OUT.json
+  python -m paper_2102_05054_amd.traffic FETCH.csv WRITE.csv COPY_BYTES OUT.json [ki|bw]
 """
 
 from __future__ import annotations
@@ -22,12 +25,20 @@ import sys
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ["csrc/ki_kernels_impl.h", "csrc/tile_engine.h", "csrc/ki_kernels.h"]
+FAMILIES = {
+    "ki": {"kernels": ("ki_pass_kernel", "ki_pass3_kernel"),
+           "sources": ["csrc/ki_kernels_impl.h", "csrc/tile_engine.h", "csrc/ki_kernels.h"],
+           "launches_per_step": 1},
+    "bw": {"kernels": ("bw_pass_kernel", "bw_pipe_kernel"),
+           "sources": ["csrc/bw_kernels.hip", "csrc/tile_engine.h", "csrc/bw_kernels.h"],
+           "launches_per_step": 2},
+}
+KERNEL_SOURCES = FAMILIES["ki"]["sources"]
 
 
-def kernel_hash() -> str:
+def kernel_hash(family: str = "ki") -> str:
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in FAMILIES[family]["sources"]:
         with open(os.path.join(HERE, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -41,11 +52,11 @@ def _per_kernel(path):
     return {k: sum(v) / len(v) for k, v in acc.items()}, {k: len(v) for k, v in acc.items()}
 
 
-def summarise(fetch_csv, write_csv, copy_bytes):
+def summarise(fetch_csv, write_csv, copy_bytes, family="ki"):
     fetch, nf = _per_kernel(fetch_csv)
     write, _ = _per_kernel(write_csv)
     copy_names = [k for k in fetch if ("copyBuffer" in k or "elementwise" in k or "vectorized" in k)
-                  and "ki_pass" not in k and fetch[k] * 1024.0 > 0.05 * copy_bytes]
+                  and "_pass" not in k and "_pipe" not in k and fetch[k] * 1024.0 > 0.05 * copy_bytes]
     if not copy_names:
         raise RuntimeError("no copy kernel in the counter runs")
     for k in copy_names:
@@ -60,10 +71,10 @@ def summarise(fetch_csv, write_csv, copy_bytes):
                for k in copy_names}
     f_factor = copy_bytes / (fetch[cname] * 1024.0)
     w_factor = copy_bytes / (write[cname] * 1024.0)
+    fam = FAMILIES[family]
     passes = {}
     for k in fetch:
-        if any(t in k for t in ("ki_pass_kernel<float", "ki_pass_kernel<double", "ki_pass3_kernel<float",
-                                "ki_pass3_kernel<double")):
+        if any(f"{t}<{r}" in k for t in fam["kernels"] for r in ("float", "double")):
             passes[k] = {
                 "fetch_bytes": fetch[k] * 1024.0 * f_factor,
                 "write_bytes": write.get(k, 0.0) * 1024.0 * w_factor,
@@ -91,12 +102,19 @@ def summarise(fetch_csv, write_csv, copy_bytes):
                 "bytes_per_launch": sum((v["fetch_bytes"] + v["write_bytes"]) * v["dispatches"]
                                         for v in main.values()) / n}
 
+    def per_step(real):
+        b = per_pass(real)
+        return None if b is None else b * fam["launches_per_step"]
+
     c64 = per_pass("float")
     return {
+        "family": family,
         # the kernel with the most dispatches (the tuned pass of the workload)
         "dominant_c64": dominant("float"),
         "dominant_c128": dominant("double"),
-        "kernel_hash": kernel_hash(),
+        "bytes_per_horner_step_c64": per_step("float"),
+        "bytes_per_horner_step_c128": per_step("double"),
+        "kernel_hash": kernel_hash(family),
         "copy_kernel": cname,
         "calibration_factors": factors,
         "copy_bytes": copy_bytes,
@@ -110,7 +128,7 @@ def summarise(fetch_csv, write_csv, copy_bytes):
 
 
 if __name__ == "__main__":
-    out = summarise(sys.argv[1], sys.argv[2], float(sys.argv[3]))
+    out = summarise(sys.argv[1], sys.argv[2], float(sys.argv[3]), sys.argv[5] if len(sys.argv) > 5 else "ki")
     with open(sys.argv[4], "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out, indent=1))

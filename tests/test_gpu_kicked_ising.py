@@ -114,6 +114,57 @@ def test_apply_filter_matrix_free_parity(dt, L, k, phi):
     assert rel(out, ref) < tol
 
 
+def _maxrel(out, ref):
+    return float(np.max(np.abs(out - ref)) / np.max(np.abs(ref)))
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("L,g", [(21, 0.9), (22, 0.9), (23, 0.9), (24, 0.9), (22, 1.4)])
+def test_apply_filter_large_states_elementwise(L, g):
+    # the single-vector passes of large states (three register layouts for
+    # 16-amplitude tiles, 14-bit low tiles for complex64 at L = 24; g = 1.4
+    # takes the swapped kick form and the two-layout pass), element-wise
+    # against the oracle's matrix-free U: the filter (Eq. (geo)), a
+    # polynomial with coefficients (Eq. (poly)) and U itself (the phase pass
+    # without psi); at L = 24 also two vectors per launch
+    say(f"apply_filter large state L={L} g={g}")
+    p = kicked_ising(L, 550 + L, g=g)
+    psi = random_state(2 ** L, 17)[0]
+    k, phi = 2, 2.1  # the prologue kick pass and two Horner passes
+    powers = []
+
+    def matvec(v):
+        r = models.ki_apply(p, v)
+        powers.append(r)
+        return r
+
+    ref = filters.geometric_sum(matvec, psi, k, phi)
+    rot = np.exp(-1j * phi)
+    u1, u2 = powers[0], powers[1] / rot  # U psi and U^2 psi
+    coeffs = np.array([0.3 - 0.2j, -1.1 + 0.4j, 0.7 + 0.9j])
+    ref_poly = coeffs[0] * psi + coeffs[1] * u1 + coeffs[2] * u2
+    with ki_op(p) as op:
+        for dt in ("c128", "c64"):
+            tol = 1e-12 * (k + 1) if dt == "c128" else 2e-7 * (k + 1) + 2e-6
+            x = to_dev(psi, _dt(dt))
+            err = _maxrel(to_np(op.apply_filter(x, k, phi)), ref)
+            assert err < tol, ("filter", dt, err)
+            err = _maxrel(to_np(op.apply_polynomial(x, coeffs)), ref_poly)
+            assert err < tol, ("polynomial", dt, err)
+            err = _maxrel(to_np(op.apply_U(x)), u1)
+            assert err < TOL_U[dt], ("U", dt, err)
+            if L == 24:
+                torch = require_gpu()
+                xx = torch.stack([x, x]).contiguous()
+                del x
+                out2 = to_np(op.apply_filter_many(xx, k, phi))
+                del xx
+                for j in range(2):
+                    err = _maxrel(out2[j], ref)
+                    assert err < tol, ("filter_many", dt, j, err)
+                del out2
+
+
 @pytest.mark.parametrize("L", [8, 12])
 def test_apply_polynomial_parity(L):
     torch = require_gpu()
