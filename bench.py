@@ -78,6 +78,8 @@ def parse():
     ap.add_argument("--filter-steps", type=int, default=0,
                     help="bw_paper: time only the block filter (--block-c128 vectors per launch, this many Horner "
                          "steps) instead of the solve")
+    ap.add_argument("--graphs", type=int, default=1, choices=[0, 1],
+                    help="ki_batched: replay the lockstep filters from captured HIP graphs (fq_set_graph_capture)")
     ap.add_argument("--profile-gemm", action="store_true",
                     help="only solves with filter order 1 (two restarts each), for counter runs of the FP64 "
                          "matrix-core basis rotation")
@@ -270,8 +272,9 @@ def batched(args):
     import numpy as np
     import torch
 
-    from paper_2102_05054_amd import arnoldi_eigs_batched, kicked_ising
+    from paper_2102_05054_amd import arnoldi_eigs_batched, kicked_ising, set_graph_capture
     from workloads import CONFIGS, config_kicked_ising
+    set_graph_capture(bool(args.graphs))
     c = CONFIGS["ki_batched"]
     nev, ncv = c["nev"], c["ncv"]
     ops, ks = [], []
@@ -332,7 +335,8 @@ def batched(args):
         "data": "synthetic (seeded kicked-Ising couplings)",
         "config": {"workload": f"kicked Ising, 256 realisations, L uniform in 12..16, 4 targets, nev={nev}, "
                                f"ncv={ncv}, k per L by the paper rule, tol={c['tol']}",
-                   "problems": nprob, "k_per_L": {str(o.L): k for o, k in zip(ops, ks)}},
+                   "problems": nprob, "k_per_L": {str(o.L): k for o, k in zip(ops, ks)},
+                   "graph_capture": bool(args.graphs)},
         "time_to_all_eigenpairs_s": {"batched c64+refine": t_total / args.steps,
                                      "batched c128": c128["time_s"] if c128 else None,
                                      "one by one c64+refine (estimated)": seq},

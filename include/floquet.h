@@ -287,6 +287,20 @@ fq_status fq_paper_parameters(int L, int nev, int* ncv_out, int* k_out);
 enum { FQ_POLICY_AUTO = 0, FQ_POLICY_TILE = 1, FQ_POLICY_PIPE = 2 };
 fq_status fq_set_kernel_policy(int policy);
 
+/*
+ * HIP-graph replay of the lockstep filters of arnoldi_eigs_batched (the
+ * batched filter steps of Sec. 5's disorder averages), process-wide:
+ *   1 (default): the k + 1 pass launches of a bucket's filter step are
+ *     captured once per precision, filter order and range of active problems
+ *     into a HIP graph and replayed at every Arnoldi step with that range;
+ *     the call then runs on a non-blocking stream of its own, after draining
+ *     the caller's stream (it returns when its work is done either way);
+ *   0: the passes are launched one by one on the caller's stream.
+ * Both compute the same arithmetic in the same order.  FQ_EINVAL for other
+ * values.  Not thread-safe with concurrent solves.
+ */
+fq_status fq_set_graph_capture(int on);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* floquet_last_error(void);
 

@@ -6,5 +6,5 @@ torch tensors for device memory and streams.
 """
 
 from .api import (FloquetOp, arnoldi_eigs_batched, brickwork, circuit, host_schur, kicked_ising,  # noqa: F401
-                  paper_parameters)
+                  paper_parameters, set_graph_capture)
 from ._lib import FloquetError, LIB_PATH  # noqa: F401

@@ -70,6 +70,7 @@ SIGNATURES = [
                                      POINTER(c_void_p), POINTER(c_double), POINTER(FqArnoldiStats), c_void_p]),
     ("floquet_last_error", ctypes.c_char_p, []),
     ("fq_set_kernel_policy", c_int, [c_int]),
+    ("fq_set_graph_capture", c_int, [c_int]),
     ("fq_host_schur", c_int, [c_int, POINTER(c_double), POINTER(c_double), POINTER(c_double)]),
     ("fq_paper_parameters", c_int, [c_int, c_int, POINTER(c_int), POINTER(c_int)]),
     ("fq_host_eigvalsh", c_int, [c_int, POINTER(c_double), POINTER(c_double)]),

@@ -310,3 +310,9 @@ def paper_parameters(L: int, nev: int):
     ncv, k = ctypes.c_int(), ctypes.c_int()
     check(lib().fq_paper_parameters(int(L), int(nev), ctypes.byref(ncv), ctypes.byref(k)), "fq_paper_parameters")
     return ncv.value, k.value
+
+
+def set_graph_capture(on: bool):
+    """HIP-graph replay of the lockstep filters of arnoldi_eigs_batched (see
+    fq_set_graph_capture in include/floquet.h); on by default."""
+    check(lib().fq_set_graph_capture(1 if on else 0), "fq_set_graph_capture")

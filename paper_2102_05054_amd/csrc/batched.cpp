@@ -12,6 +12,13 @@
 // of krylov.cpp (complex64 phase, FP64 warm-started refinement, the same
 // restart and stopping rules and the same reduction order of every
 // projection); only the interleaving of problems differs.
+//
+// With graph capture on (fq_set_graph_capture, the default), the k + 1 pass
+// launches of a lockstep filter are captured once per (precision, range of
+// active problems, filter order) into a HIP graph and replayed at every
+// Arnoldi step with that range; the solve then runs on a stream of its own
+// (the caller's stream is drained first and the call returns when the work
+// is done, as without graphs).  Graphs hold kernel launches only.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -128,8 +135,19 @@ struct Bucket {
   bool have32 = false, have64 = false;
   // timing of the batch
   double t_filter = 0.0, t_restart = 0.0, t_begin = 0.0;
+  // replayable filters (graph capture on): key (complex64?, first list slot,
+  // problems, filter order)
+  bool graphs = false;
+  struct Graph {
+    bool c64;
+    unsigned pos0, n;
+    int k;
+    hipGraphExec_t exec;
+  };
+  std::vector<Graph> gcache;
 
   ~Bucket() {
+    for (Graph& g : gcache) (void)hipGraphExecDestroy(g.exec);
     if (mem) (void)hipFree(mem);
     if (hmem) (void)hipHostFree(hmem);
   }
@@ -319,6 +337,53 @@ void fresh_phase(Bucket& B, Prob& p, Ph ph, bool check_true, bool early, double 
 }
 
 // ---------------------------------------------------------------------------
+// The batched filter of the problems list[pos0 .. pos0 + n), replayed from a
+// captured graph when graph capture is on
+// ---------------------------------------------------------------------------
+std::atomic<int> g_graph_capture{1};
+
+template <typename Real>
+fq_status run_filter(Bucket& B, const KiBatchShape& sh, int k, const KiDesc<Real>* desc, unsigned pos0, unsigned n) {
+  const bool c64 = sizeof(Real) == 4;
+  // the single-workgroup form is one launch for all k steps already
+  if (!B.graphs || sh.single || k < 8) return ki_batch_filter<Real>(sh, k, desc, B.list + pos0, n, B.s);
+  for (const Bucket::Graph& g : B.gcache)
+    if (g.c64 == c64 && g.pos0 == pos0 && g.n == n && g.k == k) {
+      FQ_HIP_CHECK(hipGraphLaunch(g.exec, B.s));
+      return FQ_OK;
+    }
+  // capture: kernel launches only (the shape is tuned and its launch
+  // attributes set by the eager runs of the autotuner)
+  FQ_HIP_CHECK(hipStreamBeginCapture(B.s, hipStreamCaptureModeThreadLocal));
+  const fq_status st = ki_batch_filter<Real>(sh, k, desc, B.list + pos0, n, B.s);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(B.s, &graph);
+  if (st != FQ_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (ec != hipSuccess || !graph) {
+    set_error(std::string("capture of the batched filter failed: ") + hipGetErrorString(ec));
+    return FQ_EDEVICE;
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) {
+    set_error(std::string("instantiation of the batched filter graph failed: ") + hipGetErrorString(ei));
+    return FQ_EDEVICE;
+  }
+  // a handful of active ranges per bucket; keep the most recent ones
+  if (B.gcache.size() >= 8) {
+    (void)hipGraphExecDestroy(B.gcache.front().exec);
+    B.gcache.erase(B.gcache.begin());
+  }
+  B.gcache.push_back(Bucket::Graph{c64, pos0, n, k, exec});
+  FQ_HIP_CHECK(hipGraphLaunch(exec, B.s));
+  return FQ_OK;
+}
+
+// ---------------------------------------------------------------------------
 // One Arnoldi step of every active problem
 // ---------------------------------------------------------------------------
 fq_status step(Bucket& B, const std::vector<Seg>& segs) {
@@ -336,10 +401,10 @@ fq_status step(Bucket& B, const std::vector<Seg>& segs) {
     if (pos0 >= pos1) continue;
     const unsigned n = pos1 - pos0;
     if (ph == Ph::C64) {
-      FQ_TRY(ki_batch_filter<float>(B.sh32, B.k, B.f32, B.list + pos0, n, B.s));
+      FQ_TRY(run_filter<float>(B, B.sh32, B.k, B.f32, pos0, n));
       FQ_HIP_CHECK(launch_b_cast_out(B.args(B.list + pos0, n), B.f32, B.s));
     } else {
-      FQ_TRY(ki_batch_filter<double>(B.sh64, B.mixed ? B.k_ref : B.k, B.f64, B.list + pos0, n, B.s));
+      FQ_TRY(run_filter<double>(B, B.sh64, B.mixed ? B.k_ref : B.k, B.f64, pos0, n));
     }
   }
   for (const Seg& g : segs) {
@@ -810,6 +875,24 @@ fq_status arnoldi_batched_solve(floquet_op* const* ops, int n_ops, const double*
       set_error("phi must be finite");
       return FQ_EINVAL;
     }
+  // graph capture needs a stream that can be captured (not the legacy null
+  // stream): the solve runs on a stream of its own, after the caller's
+  const bool graphs = g_graph_capture.load() != 0;
+  hipStream_t own = nullptr;
+  if (graphs) {
+    FQ_HIP_CHECK(hipStreamSynchronize(s));
+    FQ_HIP_CHECK(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+    s = own;
+  }
+  struct StreamGuard {
+    hipStream_t st;
+    ~StreamGuard() {
+      if (st) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+      }
+    }
+  } guard{own};
   const size_t nprob = size_t(n_ops) * n_phi;
   std::fill(evals_host, evals_host + 2 * size_t(nev) * nprob, 0.0);
   if (resid_host) std::fill(resid_host, resid_host + size_t(nev) * nprob, 0.0);
@@ -896,6 +979,7 @@ fq_status arnoldi_batched_solve(floquet_op* const* ops, int n_ops, const double*
         B.o = o;
         B.mixed = o->filter_dtype == FQ_C64;
         B.s = s;
+        B.graphs = graphs;
         B.P.assign(all.begin() + c0, all.begin() + c1);
         const fq_status st = run_bucket(B, out);
         if (st != FQ_OK) {
@@ -926,4 +1010,18 @@ fq_status arnoldi_batched_solve(floquet_op* const* ops, int n_ops, const double*
   return worst;
 }
 
+fq_status set_graph_capture(int on) {
+  if (on != 0 && on != 1) {
+    set_error("fq_set_graph_capture: on must be 0 or 1");
+    return FQ_EINVAL;
+  }
+  g_graph_capture.store(on);
+  return FQ_OK;
+}
+
 }  // namespace fq
+
+extern "C" fq_status fq_set_graph_capture(int on) {
+  fq::clear_error();
+  return fq::set_graph_capture(on);
+}

@@ -57,5 +57,7 @@ fq_status arnoldi_batched_solve(floquet_op* const* ops, int n_ops, const double*
                                 const fq_arnoldi_opts* o, const int* k_per_op, double* evals_host,
                                 void* const* evecs_dev, double* resid_host, fq_arnoldi_stats* stats,
                                 hipStream_t s);
+// Graph replay of the lockstep filters (fq_set_graph_capture): 0 or 1.
+fq_status set_graph_capture(int on);
 
 }  // namespace fq

@@ -40,6 +40,16 @@ def test_library_exports_every_declared_symbol():
     assert set(_declared_functions()) <= bound
 
 
+def test_graph_capture_switch():
+    # process-wide switch of the batched solver's graph replay (host only)
+    from paper_2102_05054_amd import _lib
+    L = _lib.lib()
+    assert L.fq_set_graph_capture(2) == _lib.FQ_EINVAL
+    assert b"0 or 1" in L.floquet_last_error()
+    assert L.fq_set_graph_capture(0) == _lib.FQ_OK
+    assert L.fq_set_graph_capture(1) == _lib.FQ_OK
+
+
 def test_invalid_arguments_are_rejected_on_host():
     from paper_2102_05054_amd import _lib
     L = _lib.lib()

@@ -153,3 +153,36 @@ def test_batched_refinement_filter_order():
     finally:
         for o in ops:
             o.close()
+
+
+@pytest.mark.parametrize("filter_dtype", ["c64", "c128"])
+def test_batched_graph_replay_matches_eager(filter_dtype):
+    # the lockstep filters replayed from captured HIP graphs (many replays with
+    # the solver's own CGS2 launches and host synchronisations between them,
+    # re-captured as problems converge) give the eager launches' results bit
+    # for bit: same eigenvalues, residuals and counts
+    require_gpu()
+    from paper_2102_05054_amd import set_graph_capture
+    params = [kicked_ising(L, 900 + 10 * L + r) for L, r in [(14, 0), (14, 1), (15, 0)]]
+    phis = [0.4, 2.0]
+    nev, ncv = 8, 30
+    ks = [_paper_k(p.L, ncv) for p in params]
+    say(f"batched graph replay {filter_dtype}: sizes {[p.L for p in params]}, k {ks}")
+    ops = [ki_op(p) for p in params]
+    runs = []
+    try:
+        for mode in (False, True, True, False):
+            set_graph_capture(mode)
+            ev, res, stats, st = _batched(ops, phis, nev, k=ks, ncv=ncv, tol=1e-10, filter_dtype=filter_dtype,
+                                          seed=4)
+            assert st == 0
+            assert res.max() <= 1e-10
+            runs.append((ev, res, [s["n_U_apps"] for s in stats], [s["n_restarts"] for s in stats]))
+    finally:
+        set_graph_capture(True)
+        for o in ops:
+            o.close()
+    for ev, res, napps, nrest in runs[1:]:
+        assert np.array_equal(ev, runs[0][0])
+        assert np.array_equal(res, runs[0][1])
+        assert napps == runs[0][2] and nrest == runs[0][3]
