@@ -56,6 +56,22 @@ def test_noalloc_single_vector_large_state_and_copy():
         assert np.array_equal(cp, psi)
 
 
+def test_noalloc_complex64_L24_wide_tiles():
+    # one complex64 vector at L = 24: the untimed default shape has the 14-bit
+    # low-bit tile of the three-layout pass; against the single-vector filter
+    torch = require_gpu()
+    say("noalloc L=24 c64 one vector")
+    p = kicked_ising(24, 1400)
+    psi = random_state(2 ** 24, 6, 1)
+    with ki_op(p) as op:
+        dpsi = to_dev(psi, torch.complex64)
+        ref = to_np(op.apply_filter(dpsi[0], 5, 0.4))
+        out = torch.empty_like(dpsi)
+        got = to_np(op.apply_filter_many_noalloc(dpsi, 5, 0.4, out))[0]
+        torch.cuda.synchronize()
+    assert _elem_err(got, ref) < _tol("c64", 5)
+
+
 def test_noalloc_argument_errors():
     torch = require_gpu()
     from paper_2102_05054_amd import FloquetError
