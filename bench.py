@@ -585,8 +585,9 @@ def cpu_baseline(p, seconds=12.0):
 def pass_roofline_L24(seconds_cap=20.0):
     """The kicked-Ising Horner pass at L = 24 (d = 16,777,216), where w and psi
     (2 x 128 MiB complex64, 2 x 256 MiB complex128) exceed the 256 MB
-    Infinity Cache, one vector per launch: average pass duration from HIP
-    events on the launch stream, 3 * d * s algorithmic bytes per pass."""
+    Infinity Cache (complex64 only just: part of its reads may still hit
+    there), one vector per launch: average pass duration from HIP events on
+    the launch stream, 3 * d * s algorithmic bytes per pass."""
     from paper_2102_05054_amd import kicked_ising
     from workloads import config_kicked_ising
     q = config_kicked_ising("ki_L20", W=1.0, L=24)
