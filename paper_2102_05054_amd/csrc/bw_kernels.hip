@@ -218,6 +218,71 @@ __global__ void __launch_bounds__(1 << TB)
   }
 }
 
+// Complex128 pass with one window group per thread that moves its data
+// between windows through LDS one plane at a time (real parts, then
+// imaginary parts): the LDS holds 8 bytes per amplitude instead of 16, so a
+// 2^11- or 2^12-amplitude tile takes 17 or 35 KB and more workgroups fit a
+// CU.  Between two windows a thread writes the real parts of its sixteen
+// amplitudes at the current window's positions, reads the real parts at the
+// next window's positions into the freed registers, and does the same for
+// the imaginary parts (three barriers instead of one; a thread only
+// rewrites positions it owns in the next layout, which nobody else reads).
+template <int WB, int TB>
+__global__ void __launch_bounds__(1 << TB)
+    bw_pass_split_kernel(BwPassArgs a, const cpx<double>* __restrict__ mats, const BwWin* __restrict__ wins,
+                         const BwGate* __restrict__ gates) {
+  using C = cpx<double>;
+  constexpr int R = 1 << WB;
+  extern __shared__ char smem_raw[];
+  double* lds = reinterpret_cast<double*>(smem_raw);
+  const uint32_t g = threadIdx.x;  // the thread's window group
+  const uint32_t item = xcd_tile(blockIdx.x, gridDim.x);
+  const TileMap tm = make_tile_map(item & ((1u << a.tile_bits) - 1u), a.n, a.c, a.p);
+  const size_t voff = size_t(item >> a.tile_bits) * a.vstride;
+  const C* __restrict__ xin = static_cast<const C*>(a.xin) + voff;
+  C* __restrict__ xout = static_cast<C*>(a.xout) + voff;
+  auto group_base = [](uint32_t gg, int b) {
+    return static_cast<int>((gg & ((1u << b) - 1u)) | ((gg >> b) << (b + WB)));
+  };
+  int b = 0;
+  if (a.nwin > 0) b = load_win(wins).b;
+  int base = group_base(g, b);
+  C v[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) v[m] = xin[tm.g(base + (m << b))];
+  for (int wi = 0; wi < a.nwin; ++wi) {
+    const WinU w = load_win(wins + wi);
+    if (wi > 0) {
+      const int nbase = group_base(g, w.b);
+#pragma unroll
+      for (int m = 0; m < R; ++m) lds[bw_phys(base + (m << b))] = v[m].x;
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < R; ++m) v[m].x = lds[bw_phys(nbase + (m << w.b))];
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < R; ++m) lds[bw_phys(base + (m << b))] = v[m].y;
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < R; ++m) v[m].y = lds[bw_phys(nbase + (m << w.b))];
+      base = nbase;
+      b = w.b;
+    }
+    window_gates<double, WB>(v, w, gates, mats);
+  }
+  const C rot = mk<double>(a.rot_re, a.rot_im);
+  const C pc = mk<double>(a.psi_coef_re, a.psi_coef_im);
+  const C* __restrict__ psi = static_cast<const C*>(a.psi) + voff;
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    const uint32_t gi = tm.g(base + (m << b));
+    C x = v[m];
+    if (a.flags & BW_ROT) x = cmul(x, rot);
+    if (a.flags & BW_ADD_PSI) x = (a.flags & BW_PSI_COEF) ? cfma(psi[gi], pc, x) : cadd(x, psi[gi]);
+    xout[gi] = x;
+  }
+}
+
 // Persistent, software-pipelined form for tiles of 2^NB amplitudes
 // (2^(NB - WB - TB) window groups per thread): each workgroup walks its
 // (vector, tile) items (XCD-aware order), and while the windows of one tile
@@ -337,6 +402,20 @@ hipError_t launch_bw_pipe(const BwPassArgs& a, unsigned nitems, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int WB, int TB>
+hipError_t launch_bw_split(const BwPassArgs& a, unsigned nitems, hipStream_t s) {
+  const size_t shmem = bw_lds_bytes(a.n, sizeof(double));
+  auto kern = bw_pass_split_kernel<WB, TB>;
+  if (shmem > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem));
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, dim3(nitems), dim3(1 << TB), shmem, s, a, static_cast<const cpx<double>*>(a.mats), a.wins,
+                     a.gates);
+  return hipGetLastError();
+}
+
 template <typename Real, int WB, int TB>
 hipError_t launch_bw_t(const BwPassArgs& a, unsigned nitems, hipStream_t s) {
   const size_t shmem = bw_lds_bytes(a.n, sizeof(cpx<Real>));
@@ -383,6 +462,15 @@ hipError_t bw_launch_pass(const BwPassArgs& a, bool c64_dt, int wb, unsigned nit
     if (wb == 3) return launch_bw_t<float, 3, 6>(a, nitems, s);
     if (wb == 2) return launch_bw_t<float, 2, 6>(a, nitems, s);
   } else {
+    // one window group per thread in 2^11- and 2^12-amplitude tiles: the
+    // plane-split form (L = 20, 4 vectors: 27.3 -> 24.2 us per U and
+    // vector; for 2^13-amplitude tiles its extra barriers cost more than the
+    // smaller LDS gains, since registers already limit those to one
+    // workgroup per CU: 651 -> 664 us per step at L = 24)
+    if (wb == 4 && tb == a.n - 4 && tb <= 8) {
+      if (tb == 8) return launch_bw_split<4, 8>(a, nitems, s);
+      if (tb == 7) return launch_bw_split<4, 7>(a, nitems, s);
+    }
     if (wb == 4) {
       if (tb == 9) return launch_bw_t<double, 4, 9>(a, nitems, s);
       if (tb == 8) return launch_bw_t<double, 4, 8>(a, nitems, s);

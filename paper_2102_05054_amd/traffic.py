@@ -29,7 +29,7 @@ FAMILIES = {
     "ki": {"kernels": ("ki_pass_kernel", "ki_pass3_kernel"),
            "sources": ["csrc/ki_kernels_impl.h", "csrc/tile_engine.h", "csrc/ki_kernels.h"],
            "launches_per_step": 1},
-    "bw": {"kernels": ("bw_pass_kernel", "bw_pipe_kernel"),
+    "bw": {"kernels": ("bw_pass_kernel", "bw_pipe_kernel", "bw_pass_split_kernel"),
            "sources": ["csrc/bw_kernels.hip", "csrc/tile_engine.h", "csrc/bw_kernels.h"],
            "launches_per_step": 2},
 }
@@ -72,17 +72,30 @@ def summarise(fetch_csv, write_csv, copy_bytes, family="ki"):
     f_factor = copy_bytes / (fetch[cname] * 1024.0)
     w_factor = copy_bytes / (write[cname] * 1024.0)
     fam = FAMILIES[family]
+
+    def real_of(name):
+        # the precision of a pass kernel from its template arguments (the
+        # plane-split brickwork pass is complex128 only)
+        for t in fam["kernels"]:
+            if "split" in t and f"{t}<" in name:
+                return "double"
+            for r in ("float", "double"):
+                if f"{t}<{r}" in name:
+                    return r
+        return None
+
     passes = {}
     for k in fetch:
-        if any(f"{t}<{r}" in k for t in fam["kernels"] for r in ("float", "double")):
+        if real_of(k):
             passes[k] = {
                 "fetch_bytes": fetch[k] * 1024.0 * f_factor,
                 "write_bytes": write.get(k, 0.0) * 1024.0 * w_factor,
                 "dispatches": nf[k],
+                "real": real_of(k),
             }
 
     def per_pass(real):
-        sel = [v for k, v in passes.items() if f"_kernel<{real}" in k]
+        sel = [v for v in passes.values() if v["real"] == real]
         n = sum(v["dispatches"] for v in sel)
         if n == 0:
             return None
@@ -92,7 +105,7 @@ def summarise(fetch_csv, write_csv, copy_bytes, family="ki"):
         # the kernels of the tuned passes: those with at least half the
         # dispatches of the most frequent one (the two tile groups of a plan
         # alternate), dispatch-weighted
-        sel = {k: v for k, v in passes.items() if f"_kernel<{real}" in k}
+        sel = {k: v for k, v in passes.items() if v["real"] == real}
         if not sel:
             return None
         top = max(v["dispatches"] for v in sel.values())
