@@ -553,7 +553,7 @@ def host_cores():
         n = len(os.sched_getaffinity(0))
     except AttributeError:
         n = os.cpu_count() or 1
-    # the GPU machine gives one GPU a 16-CPU share, whatever the machine shows
+    # a one-GPU job gets a 16-CPU share of the host, whatever the machine shows
     return max(1, min(n, 16))
 
 
