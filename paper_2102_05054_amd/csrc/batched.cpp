@@ -147,6 +147,8 @@ struct Bucket {
   std::vector<Graph> gcache;
 
   ~Bucket() {
+    // replays may still be in flight on an early return
+    if (!gcache.empty()) (void)hipStreamSynchronize(s);
     for (Graph& g : gcache) (void)hipGraphExecDestroy(g.exec);
     if (mem) (void)hipFree(mem);
     if (hmem) (void)hipHostFree(hmem);
