@@ -32,21 +32,35 @@ void givens(zd x, zd y, double* c, zd* s) {
   *s = (x / ax) * std::conj(y) / r;
 }
 
+// The rotations work on the interleaved (re, im) doubles of the column-major
+// storage, written out in real arithmetic so that the compiler emits plain
+// FMAs (and vectorises the column form over rows).
+
 // rows k, k+1 of A, columns [j0, j1):  A <- G A
 void rot_rows(ZMat& A, int k, int j0, int j1, double c, zd s) {
-  for (int j = j0; j < j1; ++j) {
-    const zd a = A(k, j), b = A(k + 1, j);
-    A(k, j) = c * a + s * b;
-    A(k + 1, j) = -std::conj(s) * a + c * b;
+  const double sr = s.real(), si = s.imag();
+  double* p = reinterpret_cast<double*>(A.a.data()) + 2 * (size_t(j0) * A.ld + k);
+  const size_t step = 2 * size_t(A.ld);
+  for (int j = j0; j < j1; ++j, p += step) {
+    const double ar = p[0], ai = p[1], br = p[2], bi = p[3];
+    p[0] = c * ar + (sr * br - si * bi);  // c a + s b
+    p[1] = c * ai + (sr * bi + si * br);
+    p[2] = c * br - (sr * ar + si * ai);  // -conj(s) a + c b
+    p[3] = c * bi - (sr * ai - si * ar);
   }
 }
 
 // columns k, k+1 of A, rows [i0, i1):  A <- A G^H
 void rot_cols(ZMat& A, int k, int i0, int i1, double c, zd s) {
+  const double sr = s.real(), si = s.imag();
+  double* __restrict__ pa = reinterpret_cast<double*>(A.a.data()) + 2 * (size_t(k) * A.ld);
+  double* __restrict__ pb = pa + 2 * size_t(A.ld);
   for (int i = i0; i < i1; ++i) {
-    const zd a = A(i, k), b = A(i, k + 1);
-    A(i, k) = c * a + std::conj(s) * b;
-    A(i, k + 1) = -s * a + c * b;
+    const double ar = pa[2 * i], ai = pa[2 * i + 1], br = pb[2 * i], bi = pb[2 * i + 1];
+    pa[2 * i] = c * ar + (sr * br + si * bi);  // c a + conj(s) b
+    pa[2 * i + 1] = c * ai + (sr * bi - si * br);
+    pb[2 * i] = c * br - (sr * ar - si * ai);  // -s a + c b
+    pb[2 * i + 1] = c * bi - (sr * ai + si * ar);
   }
 }
 
@@ -58,24 +72,49 @@ struct ZRot {
 };
 
 // Z <- Z G_1^H G_2^H ... for the recorded rotations in order.  Applied
-// after the iteration, a block of 32 rows of Z at a time (the block's two
-// columns of each rotation stay in cache across the rotations).
+// after the iteration on a copy of Z with the real and imaginary parts in
+// separate arrays (the rotation of two columns is then four contiguous
+// streams, which the compiler vectorises), a block of 64 rows at a time (the
+// block's two columns of each rotation stay in cache across the rotations).
 void apply_z_rotations(ZMat& Z, const std::vector<ZRot>& rots) {
   const int n = Z.n;
-  for (int r0 = 0; r0 < n; r0 += 32) {
-    const int r1 = r0 + 32 < n ? r0 + 32 : n;
-    for (const ZRot& g : rots) rot_cols(Z, g.k, r0, r1, g.c, g.s);
+  std::vector<double> re(size_t(n) * n), im(size_t(n) * n);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+      re[size_t(j) * n + i] = Z(i, j).real();
+      im[size_t(j) * n + i] = Z(i, j).imag();
+    }
+  for (int r0 = 0; r0 < n; r0 += 64) {
+    const int r1 = r0 + 64 < n ? r0 + 64 : n;
+    for (const ZRot& g : rots) {
+      const double c = g.c, sr = g.s.real(), si = g.s.imag();
+      double* __restrict__ ar = re.data() + size_t(g.k) * n;
+      double* __restrict__ ai = im.data() + size_t(g.k) * n;
+      double* __restrict__ br = ar + n;
+      double* __restrict__ bi = ai + n;
+      for (int i = r0; i < r1; ++i) {
+        const double xr = ar[i], xi = ai[i], yr = br[i], yi = bi[i];
+        ar[i] = c * xr + (sr * yr + si * yi);  // c a + conj(s) b
+        ai[i] = c * xi + (sr * yi - si * yr);
+        br[i] = c * yr - (sr * xr - si * xi);  // -s a + c b
+        bi[i] = c * yi - (sr * xi + si * xr);
+      }
+    }
   }
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) Z(i, j) = zd(re[size_t(j) * n + i], im[size_t(j) * n + i]);
 }
 
 void hessenberg(ZMat& A, ZMat& Z) {
   const int n = A.n;
   std::vector<zd> v(n), p(n), q(n);
   for (int k = 0; k + 2 < n; ++k) {
-    double xn = 0.0;
-    for (int i = k + 1; i < n; ++i) xn += std::norm(A(i, k));
-    xn = std::sqrt(xn);
-    if (xn == 0.0) continue;
+    // nothing below the subdiagonal (the Arnoldi part of a projected
+    // matrix is Hessenberg already): no reflection
+    double tail = 0.0;
+    for (int i = k + 2; i < n; ++i) tail += std::norm(A(i, k));
+    if (tail == 0.0) continue;
+    const double xn = std::sqrt(tail + std::norm(A(k + 1, k)));
     const zd x0 = A(k + 1, k);
     const zd ph = std::abs(x0) > 0 ? x0 / std::abs(x0) : zd(1, 0);
     // v = x + ph*||x|| e1, P = I - 2 v v^H / (v^H v), P x = -ph ||x|| e1
