@@ -222,6 +222,28 @@ void single_shape(int L, int* rb, int* tb) {
   *rb = L - t;
 }
 
+KiPlan make_plan_chunk(int L, int c) {
+  KiPlan pl;
+  const int tot = L + c;
+  const int nlo = (tot + 1) / 2, nhi = tot - nlo;
+  if (c < 1 || nhi <= c || nlo > 13) return pl;  // ngroups = 0: no such plan
+  pl.ngroups = 2;
+  KiGroup& lo = pl.grp[0];
+  lo.n = nlo;
+  lo.c = nlo;
+  lo.p = nlo;
+  lo.kbits = (1u << nlo) - 1u;
+  lo.ntiles = 1u << (L - nlo);
+  KiGroup& hi = pl.grp[1];
+  hi.n = nhi;
+  hi.c = c;
+  hi.p = nlo;
+  hi.kbits = ((1u << nhi) - 1u) & ~((1u << c) - 1u);
+  hi.ntiles = 1u << (L - nhi);
+  for (int i = 0; i < 2; ++i) pass_shape(pl.grp[i].n, pl.grp[i].ntiles, &pl.grp[i].rb, &pl.grp[i].tb);
+  return pl;
+}
+
 KiPlan make_plan(int L, bool c64_dt, bool wide) {
   KiPlan pl;
   // chunk of contiguous amplitudes in the high-bit tiles: 64 bytes, or 32

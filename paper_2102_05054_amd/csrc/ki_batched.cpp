@@ -187,6 +187,14 @@ std::vector<KiBatchShape> ki_batch_candidates(int L, bool sw, bool c64_dt) {
     bool dup = false;
     for (const KiPlan& o : plans3) dup = dup || (same_plan(o, wide) && o.grp[0].n == wide.grp[0].n);
     if (!dup && plan_ok(wide, L, true)) plans3.push_back(wide);
+    // high-bit tiles of 128-byte chunks (one more contiguous bit): fewer,
+    // longer runs per row of the state in the high-bit pass
+    KiPlan wide_chunk = make_plan_chunk(L, c64_dt ? 4 : 3);
+    for (int i = 0; i < wide_chunk.ngroups; ++i) {
+      wide_chunk.grp[i].rb = 4;
+      wide_chunk.grp[i].tb = wide_chunk.grp[i].n - 4;
+    }
+    if (wide_chunk.ngroups == 2 && plan_ok(wide_chunk, L, true)) plans3.push_back(wide_chunk);
     for (const KiPlan& q : plans3) {
       bool all4 = q.ngroups == 2;
       for (int i = 0; i < q.ngroups; ++i) all4 = all4 && q.grp[i].rb == 4;

@@ -58,6 +58,9 @@ void single_shape(int L, int* rb, int* tb);
 // Tile plan of a chain of L sites; wide admits the 14-bit complex64 tiles of
 // the three-layout pass (direct kick form only).
 KiPlan make_plan(int L, bool c64_dt, bool wide);
+// Two-group plan with c contiguous bits (the chunk) in the high-bit tiles;
+// ngroups = 0 if the tiles would exceed 13 bits.
+KiPlan make_plan_chunk(int L, int c);
 // Flags the three-layout pass takes: the phase, optionally + psi (with a
 // coefficient); not the input scale of the first pass.
 inline bool pass3_flags_ok(int flags) {
