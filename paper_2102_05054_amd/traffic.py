@@ -45,11 +45,21 @@ def kernel_hash(family: str = "ki") -> str:
 
 
 def _per_kernel(path):
+    """Average counter value and dispatch count per kernel, over the
+    dispatches of the kernel's largest grid: the launches over all vectors of
+    the profiled filter (the autotuner also times sub-batches of fewer
+    vectors, whose launches move fewer bytes)."""
     acc = defaultdict(list)
     with open(path) as f:
         for r in csv.DictReader(f):
-            acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
-    return {k: sum(v) / len(v) for k, v in acc.items()}, {k: len(v) for k, v in acc.items()}
+            acc[r["Kernel_Name"]].append((int(r.get("Grid_Size") or 0), float(r["Counter_Value"])))
+    avg, cnt = {}, {}
+    for k, v in acc.items():
+        gmax = max(g for g, _ in v)
+        vals = [x for g, x in v if g == gmax]
+        avg[k] = sum(vals) / len(vals)
+        cnt[k] = len(vals)
+    return avg, cnt
 
 
 def summarise(fetch_csv, write_csv, copy_bytes, family="ki"):
