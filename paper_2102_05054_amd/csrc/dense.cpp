@@ -108,6 +108,8 @@ void apply_z_rotations(ZMat& Z, const std::vector<ZRot>& rots) {
 void hessenberg(ZMat& A, ZMat& Z) {
   const int n = A.n;
   std::vector<zd> v(n), p(n), q(n);
+  std::vector<int> nz;  // rows where the reflector is non-zero
+  nz.reserve(n);
   for (int k = 0; k + 2 < n; ++k) {
     // nothing below the subdiagonal (the Arnoldi part of a projected
     // matrix is Hessenberg already): no reflection
@@ -118,19 +120,26 @@ void hessenberg(ZMat& A, ZMat& Z) {
     const zd x0 = A(k + 1, k);
     const zd ph = std::abs(x0) > 0 ? x0 / std::abs(x0) : zd(1, 0);
     // v = x + ph*||x|| e1, P = I - 2 v v^H / (v^H v), P x = -ph ||x|| e1
-    for (int i = 0; i < n; ++i) v[i] = 0;
-    for (int i = k + 1; i < n; ++i) v[i] = A(i, k);
-    v[k + 1] += ph * xn;
+    nz.clear();
+    v[k + 1] = x0 + ph * xn;
+    nz.push_back(k + 1);
+    for (int i = k + 2; i < n; ++i) {
+      v[i] = A(i, k);
+      if (v[i] != zd(0, 0)) nz.push_back(i);
+    }
     double vn = 0.0;
-    for (int i = k + 1; i < n; ++i) vn += std::norm(v[i]);
+    for (int i : nz) vn += std::norm(v[i]);
     if (vn == 0.0) continue;
     const double tau = 2.0 / vn;
+    // Only the rows (and columns) in nz change.  A Krylov-Schur restart
+    // matrix (triangular block, one coupling row, Hessenberg rest) gives
+    // two-entry reflectors, so these steps are O(n) instead of O(n^2).
     // A <- P A
     for (int j = 0; j < n; ++j) {
       zd s = 0;
-      for (int i = k + 1; i < n; ++i) s += std::conj(v[i]) * A(i, j);
+      for (int i : nz) s += std::conj(v[i]) * A(i, j);
       s *= tau;
-      for (int i = k + 1; i < n; ++i) A(i, j) -= v[i] * s;
+      for (int i : nz) A(i, j) -= v[i] * s;
     }
     // A <- A P, Z <- Z P, column by column (contiguous in memory):
     // p = A v, q = Z v, then column j -= tau * conj(v_j) * p (resp. q)
@@ -138,7 +147,7 @@ void hessenberg(ZMat& A, ZMat& Z) {
       p[i] = 0;
       q[i] = 0;
     }
-    for (int j = k + 1; j < n; ++j) {
+    for (int j : nz) {
       const zd vj = v[j];
       const zd* a = &A(0, j);
       const zd* z = &Z(0, j);
@@ -147,7 +156,7 @@ void hessenberg(ZMat& A, ZMat& Z) {
         q[i] += z[i] * vj;
       }
     }
-    for (int j = k + 1; j < n; ++j) {
+    for (int j : nz) {
       const zd f = tau * std::conj(v[j]);
       zd* a = &A(0, j);
       zd* z = &Z(0, j);
