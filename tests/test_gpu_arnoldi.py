@@ -5,7 +5,7 @@ import math
 import numpy as np
 import pytest
 
-from gpu_util import ki_op, rel, require_gpu, say, to_dev, to_np
+from gpu_util import dense_closest, ki_op, memo, rel, require_gpu, say, to_dev, to_np
 from oracle import eig, models
 from workloads import CONFIGS, config_kicked_ising, kicked_ising
 
@@ -42,8 +42,9 @@ def test_ki_L10_workload(filter_dtype):
 def test_random_targets(L, phi, nev, k, ncv):
     say(f"arnoldi L={L} phi={phi}")
     p = kicked_ising(L, 900 + L)
-    U = models.ki_dense(p)
-    om_ref, _ = eig.full_closest(U, nev, phi)
+    key = ("ki", L, 900 + L)
+    U = memo(key, lambda: models.ki_dense(p))
+    om_ref, _ = dense_closest(key, U, nev, phi)
     with ki_op(p) as op:
         ev, _, res, stats, st = op.arnoldi_eigs(nev, phi, k=k, ncv=ncv, tol=1e-10, seed=3, want_vectors=False)
     assert np.max(np.abs(ev - om_ref)) < 1e-12
@@ -144,8 +145,9 @@ def test_paper_rule_defaults_match_zgeev(L, nev, phi, filter_dtype, block):
     # (Sec. 5, Table "bench" caption), against full diagonalisation
     say(f"paper-rule defaults L={L} {filter_dtype} block {block}")
     p = kicked_ising(L, 60 + L)
-    U = models.ki_dense(p)
-    om_ref, _ = eig.full_closest(U, nev, phi)
+    key = ("ki", L, 60 + L)
+    U = memo(key, lambda: models.ki_dense(p))
+    om_ref, _ = dense_closest(key, U, nev, phi)
     ncv = max(int(math.floor(2 ** (L / 2 + 1))), 2 * nev + 1)
     k = int(math.floor(0.8 * 2 ** (L + 1) / ncv))
     with ki_op(p) as op:

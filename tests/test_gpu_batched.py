@@ -7,7 +7,7 @@ import math
 import numpy as np
 import pytest
 
-from gpu_util import bw_op, ki_op, require_gpu, say, to_np
+from gpu_util import bw_op, dense_closest, ki_op, require_gpu, say, to_np
 from oracle import eig, models
 from workloads import brickwork, kicked_ising
 
@@ -40,7 +40,7 @@ def test_batched_against_dense(filter_dtype):
         for i, p in enumerate(params):
             U = models.ki_dense(p)
             for j, phi in enumerate(phis):
-                om_ref, _ = eig.full_closest(U, nev, phi)
+                om_ref, _ = dense_closest(("ki", p.L, 700 + 10 * specs[i][0] + specs[i][1]), U, nev, phi)
                 err = np.max(np.abs(ev[i, j] - om_ref))
                 assert err < 1e-12, (p.L, phi, err)
                 assert res[i, j].max() <= 1e-10

@@ -4,7 +4,7 @@ against full diagonalisation and the oracle's matrix-free U."""
 import numpy as np
 import pytest
 
-from gpu_util import bw_op, ki_op, require_gpu, say, to_dev, to_np
+from gpu_util import bw_op, dense_closest, ki_op, memo, require_gpu, say, to_dev, to_np
 from oracle import eig, models
 from workloads import CONFIGS, brickwork, config_kicked_ising, kicked_ising, start_vector
 
@@ -40,8 +40,9 @@ def test_block_ragged_ncv(L, phi, nev, k, ncv, block):
     # ncv not a multiple of the block (the basis uses floor(ncv / b) * b), nev < b
     say(f"block arnoldi L={L} ncv={ncv} b={block}")
     p = kicked_ising(L, 900 + L)
-    U = models.ki_dense(p)
-    om_ref, _ = eig.full_closest(U, nev, phi)
+    key = ("ki", L, 900 + L)
+    U = memo(key, lambda: models.ki_dense(p))
+    om_ref, _ = dense_closest(key, U, nev, phi)
     with ki_op(p) as op:
         ev, _, res, stats, st = op.arnoldi_eigs(nev, phi, k=k, ncv=ncv, tol=1e-10, seed=3, want_vectors=False,
                                                 block=block)

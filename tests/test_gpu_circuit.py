@@ -5,7 +5,7 @@ oracle's dense and matrix-free U."""
 import numpy as np
 import pytest
 
-from gpu_util import bw_op, circ_op, rel, require_gpu, say, to_dev, to_np
+from gpu_util import bw_op, circ_op, memo, rel, require_gpu, say, to_dev, to_np
 from oracle import eig, filters, models
 from workloads import brickwork, circuit, circuit_from_brickwork, random_state
 
@@ -25,7 +25,11 @@ def test_circuit_U_and_filter_parity(dt, L, depth):
     say(f"circuit U/filter L={L} depth={depth} {dt}")
     p = circuit(L, 800 + L, depth=depth)
     psi = random_state(2 ** L, 21)[0]
-    mv = (lambda v, U=models.circuit_dense(p): U @ v) if L <= 12 else (lambda v: models.circuit_apply(p, v))
+    if L <= 12:
+        U = memo(("circuit", L, 800 + L, depth), lambda: models.circuit_dense(p))
+        mv = lambda v: U @ v  # noqa: E731
+    else:
+        mv = lambda v: models.circuit_apply(p, v)  # noqa: E731
     with circ_op(p) as op:
         out_u = to_np(op.apply_U(to_dev(psi, _dt(dt))))
         out_f = to_np(op.apply_filter(to_dev(psi, _dt(dt)), 9, 0.4))

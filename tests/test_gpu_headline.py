@@ -37,7 +37,7 @@ def oracle_residuals(p, evals, vecs):
     time on host threads (NumPy releases the GIL inside its loops)."""
     def one(n):
         return float(np.linalg.norm(models.ki_apply(p, vecs[n]) - evals[n] * vecs[n]))
-    with cf.ThreadPoolExecutor(max_workers=8) as ex:
+    with cf.ThreadPoolExecutor(max_workers=16) as ex:
         return np.array(list(ex.map(one, range(len(evals)))))
 
 
@@ -110,8 +110,11 @@ def closed_form_spectrum(p):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("g", [0.0, math.pi / 2])
-@pytest.mark.parametrize("L,dtype,block", [(16, "c128", 1), (16, "c64", 4), (20, "c128", 2), (20, "c64", 4)])
+# L = 16 in both precisions at both special points; L = 20 once per special
+# point, one precision each (a solve there takes 20-40 s)
+@pytest.mark.parametrize("L,dtype,block,g", [(16, "c128", 1, 0.0), (16, "c64", 4, 0.0),
+                                             (16, "c128", 1, math.pi / 2), (16, "c64", 4, math.pi / 2),
+                                             (20, "c128", 2, 0.0), (20, "c64", 4, math.pi / 2)])
 def test_completeness_closed_form(L, dtype, block, g):
     if L == 16:
         c = CONFIGS["ki_L16"]
