@@ -594,11 +594,15 @@ uint64_t window_step(const std::vector<PGate>& g, uint64_t done, int b, int wb, 
 // Fewest windows: a breadth-first search over the applied-gate sets, one
 // window placement (b = 0 .. n - wb) per step.  The greedy placement misses
 // windows that straddle two earlier ones (a brickwork pass of 13 bits takes 6
-// windows greedily, 4 this way).  A brickwork pass reaches a few hundred
-// sets; programs of more than 64 gates, or whose search exceeds 2^16 sets,
-// keep the greedy schedule.
-void schedule_windows(const std::vector<PGate>& g, int n, int wb, size_t kMaxGates, std::vector<BwWin>* wins,
-                      std::vector<BwGate>* out) {
+// windows greedily, 4 this way).  Among the shortest schedules the first and
+// the last window sit as high as possible, up to line_bits: the tile kernels
+// apply them on the way in from and out to global memory, where a window at
+// bit b leaves runs of 2^b consecutive amplitudes across the lanes (whole
+// 128-byte lines from b = line_bits on).  A brickwork pass reaches a few
+// hundred sets; programs of more than 64 gates, or whose search passes 2^16
+// sets, keep the greedy schedule.
+void schedule_windows(const std::vector<PGate>& g, int n, int wb, size_t kMaxGates, int line_bits,
+                      std::vector<BwWin>* wins, std::vector<BwGate>* out) {
   const size_t G = g.size();
   if (G == 0) return;
   if (G > 64 || n < wb) {
@@ -606,31 +610,55 @@ void schedule_windows(const std::vector<PGate>& g, int n, int wb, size_t kMaxGat
     return;
   }
   const uint64_t full = G == 64 ? ~uint64_t(0) : (uint64_t(1) << G) - 1u;
-  std::unordered_map<uint64_t, std::pair<uint64_t, int>> prev;  // set -> (previous set, window bit)
-  std::deque<uint64_t> queue{0};
-  prev.emplace(0, std::make_pair(uint64_t(0), -1));
-  bool found = false;
-  while (!queue.empty() && !found) {
-    const uint64_t s = queue.front();
-    queue.pop_front();
+  struct Node {
+    int level, score;  // windows so far; score of the first window
+    uint64_t from;     // best predecessor set
+    int b;             // bit of the window from it
+  };
+  std::unordered_map<uint64_t, Node> node;
+  std::vector<uint64_t> order{0};  // breadth-first order
+  node.emplace(0, Node{0, 0, 0, -1});
+  int depth = -1, best = -1, best_b = -1;
+  uint64_t best_from = 0;
+  bool overflow = false;
+  for (size_t qi = 0; qi < order.size() && !overflow; ++qi) {
+    const uint64_t s = order[qi];
+    const Node ns = node.at(s);
+    if (depth >= 0 && ns.level >= depth) break;  // no shorter schedule remains
     for (int b = 0; b + wb <= n; ++b) {
       const uint64_t t = window_step(g, s, b, wb, kMaxGates, nullptr);
-      if (t == s || prev.count(t)) continue;
-      prev.emplace(t, std::make_pair(s, b));
+      if (t == s) continue;
+      const int score = ns.level == 0 ? std::min(b, line_bits) : ns.score;
       if (t == full) {
-        found = true;
-        break;
+        depth = ns.level + 1;
+        if (score + std::min(b, line_bits) > best) {
+          best = score + std::min(b, line_bits);
+          best_from = s;
+          best_b = b;
+        }
+        continue;
       }
-      queue.push_back(t);
+      auto it = node.find(t);
+      if (it == node.end()) {
+        if (node.size() >= (size_t(1) << 16)) {
+          overflow = true;
+          break;
+        }
+        node.emplace(t, Node{ns.level + 1, score, s, b});
+        order.push_back(t);
+      } else if (it->second.level == ns.level + 1 && score > it->second.score) {
+        it->second.score = score;
+        it->second.from = s;
+        it->second.b = b;
+      }
     }
-    if (prev.size() > (size_t(1) << 16)) break;
   }
-  if (!found) {
+  if (overflow || best < 0) {
     schedule_windows_greedy(g, n, wb, kMaxGates, wins, out);
     return;
   }
-  std::vector<int> bits;
-  for (uint64_t s = full; s != 0; s = prev[s].first) bits.push_back(prev[s].second);
+  std::vector<int> bits{best_b};
+  for (uint64_t s = best_from; s != 0; s = node.at(s).from) bits.push_back(node.at(s).b);
   std::reverse(bits.begin(), bits.end());
   uint64_t done = 0;
   for (int b : bits) {
@@ -641,6 +669,11 @@ void schedule_windows(const std::vector<PGate>& g, int n, int wb, size_t kMaxGat
     for (size_t j : sel)
       out->push_back(BwGate{static_cast<int8_t>(g[j].width), static_cast<int8_t>(g[j].q - b),
                             static_cast<int16_t>(g[j].mat)});
+  }
+  if (done != full) {  // cannot happen: every step of the search applied its gates
+    wins->clear();
+    out->clear();
+    schedule_windows_greedy(g, n, wb, kMaxGates, wins, out);
   }
 }
 
@@ -755,7 +788,7 @@ fq_status build_program(floquet_op* op, bool c64_dt, std::shared_ptr<BwProgram>*
     std::vector<BwWin> wins;
     std::vector<BwGate> gl;
     if (!g.empty())
-      schedule_windows(g, ps.n, ps.wb, kBwWindowGates, &wins, &gl);
+      schedule_windows(g, ps.n, ps.wb, kBwWindowGates, c64_dt ? 4 : 3, &wins, &gl);
     ps.nwin = static_cast<int>(wins.size());
     FQ_HIP_CHECK(hipMalloc(&ps.wins, std::max<size_t>(1, wins.size()) * sizeof(BwWin)));
     FQ_HIP_CHECK(hipMalloc(&ps.gates, std::max<size_t>(1, gl.size()) * sizeof(BwGate)));
