@@ -94,6 +94,23 @@ def ki_dense(p) -> np.ndarray:
     return phase[:, None] * K
 
 
+_ENERGIES = {}
+
+
+def _ki_energies_kept(L: int, J: Sequence[float], h: Sequence[float], periodic: bool) -> np.ndarray:
+    """ki_energies, kept for the last few chains: E(s) of a chain does not
+    change between applications, and at L = 20 it costs ~10x the kicks.
+    The returned array is shared; callers only read it."""
+    key = (L, np.asarray(J, dtype=np.float64).tobytes(), np.asarray(h, dtype=np.float64).tobytes(), bool(periodic))
+    E = _ENERGIES.get(key)
+    if E is None:
+        E = ki_energies(L, J, h, periodic)
+        if len(_ENERGIES) >= 4:
+            _ENERGIES.clear()
+        _ENERGIES[key] = E
+    return E
+
+
 def ki_apply(p, psi: np.ndarray) -> np.ndarray:
     """Matrix-free U psi: one 2x2 kick per site on the reshaped state, then D."""
     L = p.L
@@ -103,7 +120,7 @@ def ki_apply(p, psi: np.ndarray) -> np.ndarray:
         x = x.reshape(2 ** (i - 1), 2, 2 ** (L - i))
         x = np.einsum("ab,xbz->xaz", k1, x)
     x = x.reshape(-1)
-    return np.exp(-1j * ki_energies(L, p.J, p.h, p.periodic)) * x
+    return np.exp(-1j * _ki_energies_kept(L, p.J, p.h, p.periodic)) * x
 
 
 def bw_gate_list(p) -> Tuple[List[Tuple[Tuple[int, ...], np.ndarray]], List[Tuple[Tuple[int, ...], np.ndarray]]]:
