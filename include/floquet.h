@@ -321,6 +321,23 @@ fq_status fq_host_schur(int n, double* a_host, double* z_host, double* w_host);
  */
 fq_status fq_host_eigvalsh(int n, double* a_host, double* w_host);
 
+/*
+ * Host-only helper exposed for testing the window schedule of the brickwork
+ * and circuit passes (Sec. 2, Eq. (U)): the gates of one pass, in acting
+ * order, on a tile of n bits (gate i on tile bits q[i] .. q[i] + w[i] - 1,
+ * w[i] = 1 or 2), grouped into windows of wb consecutive tile bits.  A window
+ * applies, in acting order, every remaining gate inside it whose earlier
+ * gates on shared bits are done (at most eight); the schedule has the fewest
+ * windows (breadth-first search; a greedy placement beyond 64 gates), and
+ * among those its first and last windows start as high as line_bits.
+ * Outputs: *nwin_out windows, window j at bit win_b[j] applying the gates
+ * order[win_first[j] .. win_first[j] + win_count[j]); every array holds at
+ * least ngates entries.  FQ_EINVAL for bad sizes, a missing array or a gate
+ * outside the tile.
+ */
+fq_status fq_host_bw_schedule(int n, int wb, int ngates, const int* q, const int* w, int line_bits,
+                              int* nwin_out, int* win_b, int* win_first, int* win_count, int* order);
+
 #ifdef __cplusplus
 }
 #endif

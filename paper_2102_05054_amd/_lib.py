@@ -74,6 +74,8 @@ SIGNATURES = [
     ("fq_host_schur", c_int, [c_int, POINTER(c_double), POINTER(c_double), POINTER(c_double)]),
     ("fq_paper_parameters", c_int, [c_int, c_int, POINTER(c_int), POINTER(c_int)]),
     ("fq_host_eigvalsh", c_int, [c_int, POINTER(c_double), POINTER(c_double)]),
+    ("fq_host_bw_schedule", c_int, [c_int, c_int, c_int, POINTER(c_int), POINTER(c_int), c_int, POINTER(c_int),
+                                    POINTER(c_int), POINTER(c_int), POINTER(c_int), POINTER(c_int)]),
     ("entanglement_entropy", c_int, [c_void_p, c_int, c_void_p, c_int, POINTER(c_double), c_void_p]),
 ]
 

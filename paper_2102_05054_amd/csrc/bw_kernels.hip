@@ -1001,3 +1001,35 @@ fq_status bw_filter(floquet_op* op, int k, double phi, const zd* coefs, fq_dtype
 }
 
 }  // namespace fq
+
+extern "C" fq_status fq_host_bw_schedule(int n, int wb, int ngates, const int* q, const int* w, int line_bits,
+                                         int* nwin_out, int* win_b, int* win_first, int* win_count,
+                                         int* order) {
+  using namespace fq;
+  clear_error();
+  const bool arrays = ngates == 0 || (q && w && win_b && win_first && win_count && order);
+  if (n < 1 || n > 30 || wb < 1 || wb > 5 || wb > n || ngates < 0 || ngates > 32767 || line_bits < 0 ||
+      !nwin_out || !arrays) {
+    set_error("fq_host_bw_schedule: bad arguments");
+    return FQ_EINVAL;
+  }
+  std::vector<PGate> g;
+  for (int i = 0; i < ngates; ++i) {
+    if ((w[i] != 1 && w[i] != 2) || q[i] < 0 || q[i] + w[i] > n || w[i] > wb) {
+      set_error("fq_host_bw_schedule: gate " + std::to_string(i) + " outside the tile or wider than a window");
+      return FQ_EINVAL;
+    }
+    g.push_back(PGate{q[i], w[i], i});
+  }
+  std::vector<BwWin> wins;
+  std::vector<BwGate> gl;
+  schedule_windows(g, n, wb, kBwWindowGates, line_bits, &wins, &gl);
+  *nwin_out = static_cast<int>(wins.size());
+  for (size_t j = 0; j < wins.size(); ++j) {
+    win_b[j] = wins[j].b;
+    win_first[j] = wins[j].first;
+    win_count[j] = wins[j].count;
+  }
+  for (size_t k = 0; k < gl.size(); ++k) order[k] = gl[k].mat;
+  return FQ_OK;
+}
