@@ -768,6 +768,10 @@ def main():
         "time_to_eigenpairs_s": {"c64+refine": t_total / steps_done, "c128": c128["time_s"] if c128 else None},
         "eigenpairs_per_s": {"c64+refine": args.nev * steps_done / t_total,
                              "c128": (args.nev / c128["time_s"]) if c128 else None},
+        # why the mixed form is not the faster one at this filter order
+        "precision_note": ("the FP64 refinement needs about one full FP64 Krylov cycle whatever its start "
+                           "(the Ritz vectors must be separated in FP64 from the eigenvectors next to the wanted "
+                           "set inside the filter's main lobe), so the complex64 phase adds to the FP64 cost"),
         "solve": {"status": int(last_status), "nconv": last_st["nconv"], "max_residual": float(last_res.max()),
                   "n_restarts": last_st["n_restarts"], "n_U_apps": last_st["n_U_apps"],
                   "n_U_apps_c64": last_st["n_U_apps_c64"], "t_refine_s": last_st["t_refine"],
