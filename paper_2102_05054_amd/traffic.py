@@ -13,6 +13,12 @@ left block with +psi).
 
 Usage:
   python -m paper_2102_05054_amd.traffic FETCH.csv WRITE.csv COPY_BYTES OUT.json [ki|bw]
+  python -m paper_2102_05054_amd.traffic --launches KERNEL_TRACE.csv OUT.json
+
+The second form averages the durations of a ``rocprofv3 --kernel-trace`` run
+per kernel and grid size: a solve launches the same pass kernel over 4 or 2
+vectors (and the tile autotuner over fewer), and the launches over all the
+vectors of a filter are the ones a roofline figure describes.
 """
 
 from __future__ import annotations
@@ -21,6 +27,7 @@ import csv
 import hashlib
 import json
 import os
+import re
 import sys
 from collections import defaultdict
 
@@ -150,7 +157,34 @@ def summarise(fetch_csv, write_csv, copy_bytes, family="ki"):
     }
 
 
-if __name__ == "__main__":
+def launch_durations(path):
+    """Per kernel name: {grid size: (dispatches, average microseconds)},
+    from a rocprofv3 kernel-trace CSV (Start/End timestamps in ns)."""
+    acc = defaultdict(lambda: defaultdict(list))
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if "Grid_Size" in r and r["Grid_Size"]:
+                grid = int(r["Grid_Size"])
+            else:
+                grid = 1
+                for ax in ("X", "Y", "Z"):
+                    grid *= int(r.get(f"Grid_Size_{ax}") or 1)
+            dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+            acc[r["Kernel_Name"]][grid].append(dur)
+    return {k: {g: (len(v), sum(v) / len(v)) for g, v in sorted(per.items())} for k, per in acc.items()}
+
+
+if __name__ == "__main__" and len(sys.argv) > 1 and sys.argv[1] == "--launches":
+    table = launch_durations(sys.argv[2])
+    rows = {k: {str(g): {"dispatches": n, "avg_us": a} for g, (n, a) in per.items()} for k, per in table.items()}
+    with open(sys.argv[3], "w") as f:
+        json.dump(rows, f, indent=1)
+    for k, per in table.items():
+        if any(x in k for x in FAMILIES["ki"]["kernels"] + FAMILIES["bw"]["kernels"]):
+            for g, (n, a) in per.items():
+                m = re.search(r"(\w+<[^>]*>)", k)
+                print(f"{m.group(1) if m else k}  grid {g}: {n} dispatches, {a:.2f} us")
+elif __name__ == "__main__":
     out = summarise(sys.argv[1], sys.argv[2], float(sys.argv[3]), sys.argv[5] if len(sys.argv) > 5 else "ki")
     with open(sys.argv[4], "w") as f:
         json.dump(out, f, indent=1)
