@@ -90,6 +90,49 @@ def test_batched_matches_single_solver():
             o.close()
 
 
+def test_batched_workload_sample_at_full_size():
+    # the disorder workload as the benchmark runs it (nev = 20, ncv = 60, k by
+    # the paper's rule per chain length, the four targets, complex64 filter +
+    # FP64 refinement, graph-replayed filter steps) on a sample of its
+    # realisations: the first three of length 16 and the first of length 15;
+    # every returned pair re-checked with the oracle's matrix-free U
+    import concurrent.futures as cf
+
+    from workloads import CONFIGS, batched_sizes, config_kicked_ising
+    require_gpu()
+    c = CONFIGS["ki_batched"]
+    sizes = batched_sizes(c["n_real"], c["L"][0], c["L"][1])
+    pick = [int(r) for r in np.flatnonzero(sizes == 16)[:3]] + [int(np.flatnonzero(sizes == 15)[0])]
+    params = [config_kicked_ising("ki_batched", realisation=r) for r in pick]
+    phis = list(c["phis"])
+    nev, ncv = c["nev"], c["ncv"]
+    ks = [_paper_k(p.L, ncv) for p in params]
+    say(f"batched workload sample: realisations {pick}, sizes {[p.L for p in params]}, k {ks}")
+    ops = [ki_op(p) for p in params]
+    try:
+        ev, res, stats, st, vecs = _batched(ops, phis, nev, k=ks, ncv=ncv, tol=c["tol"], filter_dtype="c64",
+                                            seed=3, want_vectors=True)
+        assert st == 0
+        for i, p in enumerate(params):
+            for j, phi in enumerate(phis):
+                q = i * len(phis) + j
+                assert stats[q]["nconv"] == nev
+                assert res[i, j].max() <= 1e-10
+                assert np.max(np.abs(np.abs(ev[i, j]) - 1)) < 1e-10
+                dist = eig.arc_distance(ev[i, j], phi)
+                assert np.all(np.diff(dist) >= -1e-13)
+                V = to_np(vecs[q])
+
+                def one(n, V=V, p=p, i=i, j=j):
+                    return float(np.linalg.norm(models.ki_apply(p, V[n]) - ev[i, j, n] * V[n]))
+                with cf.ThreadPoolExecutor(max_workers=16) as ex:
+                    r_or = np.array(list(ex.map(one, range(nev))))
+                assert r_or.max() <= 1e-10, (p.L, phi, r_or.max())
+    finally:
+        for o in ops:
+            o.close()
+
+
 def test_batched_mixed_models_fall_back():
     # brickwork goes through the one-by-one path inside the call
     require_gpu()
