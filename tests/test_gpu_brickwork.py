@@ -108,6 +108,29 @@ def test_apply_filter_parity(dt, L, k, phi):
     assert rel(out, ref) < tol
 
 
+@pytest.mark.timeout(300)
+def test_apply_filter_L24_workload_elementwise():
+    # the brick-wall filter as the L = 24 benchmark runs it (the workload's
+    # seeded Haar circuit, both passes with e^{-i phi} and +psi fused into the
+    # second, complex64 through the pipelined tile kernel), element-wise
+    # against the oracle's geometric sum (Eq. (geo)); complex128 beside it
+    from workloads import CONFIGS
+    c = CONFIGS["bw_L24"]
+    p = brickwork(c["L"], c["seed"])
+    psi = random_state(2 ** c["L"], 12)[0]
+    k, phi = 2, 0.7
+    ref = filters.geometric_sum(lambda v: models.bw_apply(p, v), psi, k, phi)
+    scale = np.max(np.abs(ref))
+    with bw_op(p) as op:
+        for dt in ("c64", "c128"):
+            say(f"bw apply_filter L=24 workload k={k} {dt}")
+            out = to_np(op.apply_filter(to_dev(psi, _dt(dt)), k, phi))
+            err = float(np.max(np.abs(out - ref)) / scale)
+            tol = 1e-12 * (k + 1) if dt == "c128" else 2e-7 * (k + 1) + 3e-6
+            assert err < tol, (dt, err)
+            del out
+
+
 def test_apply_polynomial_parity():
     torch = require_gpu()
     p = brickwork(9, 71)
