@@ -222,23 +222,25 @@ __global__ void __launch_bounds__(1 << TB)
   }
 }
 
-// Complex128 pass with one window group per thread that moves its data
+// Tile pass with one window group per thread kept in registers, moved
 // between windows through LDS one plane at a time (real parts, then
-// imaginary parts): the LDS holds 8 bytes per amplitude instead of 16, so a
-// 2^11- or 2^12-amplitude tile takes 17 or 35 KB and more workgroups fit a
-// CU.  Between two windows a thread writes the real parts of its sixteen
-// amplitudes at the current window's positions, reads the real parts at the
-// next window's positions into the freed registers, and does the same for
-// the imaginary parts (three barriers instead of one; a thread only
-// rewrites positions it owns in the next layout, which nobody else reads).
-template <int WB, int TB>
+// imaginary parts): the LDS holds sizeof(Real) bytes per amplitude instead
+// of twice that, so that more workgroups fit a CU (complex128 2^11 / 2^12
+// tiles: 17 / 35 KB; complex64 2^13 / 2^14 tiles: 34 / 68 KB).  Between two
+// windows a thread writes the real parts of its sixteen amplitudes at the
+// current window's positions, reads the real parts at the next window's
+// positions into the freed registers, and does the same for the imaginary
+// parts (three barriers instead of one; a thread only rewrites positions it
+// owns in the next layout, which nobody else reads).  The first window is
+// applied on the way in from global memory, the last on the way out.
+template <typename Real, int WB, int TB>
 __global__ void __launch_bounds__(1 << TB)
-    bw_pass_split_kernel(BwPassArgs a, const cpx<double>* __restrict__ mats, const BwWin* __restrict__ wins,
+    bw_pass_split_kernel(BwPassArgs a, const cpx<Real>* __restrict__ mats, const BwWin* __restrict__ wins,
                          const BwGate* __restrict__ gates) {
-  using C = cpx<double>;
+  using C = cpx<Real>;
   constexpr int R = 1 << WB;
   extern __shared__ char smem_raw[];
-  double* lds = reinterpret_cast<double*>(smem_raw);
+  Real* lds = reinterpret_cast<Real*>(smem_raw);
   const uint32_t g = threadIdx.x;  // the thread's window group
   const uint32_t item = xcd_tile(blockIdx.x, gridDim.x);
   const TileMap tm = make_tile_map(item & ((1u << a.tile_bits) - 1u), a.n, a.c, a.p);
@@ -272,10 +274,10 @@ __global__ void __launch_bounds__(1 << TB)
       base = nbase;
       b = w.b;
     }
-    window_gates<double, WB>(v, w, gates, mats);
+    window_gates<Real, WB>(v, w, gates, mats);
   }
-  const C rot = mk<double>(a.rot_re, a.rot_im);
-  const C pc = mk<double>(a.psi_coef_re, a.psi_coef_im);
+  const C rot = mk<Real>(static_cast<Real>(a.rot_re), static_cast<Real>(a.rot_im));
+  const C pc = mk<Real>(static_cast<Real>(a.psi_coef_re), static_cast<Real>(a.psi_coef_im));
   const C* __restrict__ psi = static_cast<const C*>(a.psi) + voff;
 #pragma unroll
   for (int m = 0; m < R; ++m) {
@@ -287,135 +289,20 @@ __global__ void __launch_bounds__(1 << TB)
   }
 }
 
-// Persistent, software-pipelined form for tiles of 2^NB amplitudes
-// (2^(NB - WB - TB) window groups per thread): each workgroup walks its
-// (vector, tile) items (XCD-aware order), and while the windows of one tile
-// run in LDS the next tile is already on its way into registers.  Tiles are
-// disjoint, so in-place passes (xin == xout) stay correct.
-template <typename Real, int WB, int TB, int NB, bool PSI>
-__global__ void __launch_bounds__(1 << TB)
-    bw_pipe_kernel(BwPassArgs a, unsigned nitems, const cpx<Real>* __restrict__ mats, const BwWin* __restrict__ wins,
-                   const BwGate* __restrict__ gates, cpx<Real>* __restrict__ xout) {
-  using C = cpx<Real>;
-  constexpr int T = 1 << TB, N = 1 << NB, NPT = N / T;
-  constexpr int GPT = 1 << (NB - WB - TB);  // window groups per thread
-  static_assert(NB - WB >= TB, "every thread owns a window group");
-  extern __shared__ char smem_raw[];
-  C* lds = reinterpret_cast<C*>(smem_raw);
-  const int tid = threadIdx.x;
-  // xin may equal xout (in-place pass): read through the same restrict pointer
-  const C* xin = xout == a.xin ? xout : static_cast<const C*>(a.xin);
-  const C* psi = static_cast<const C*>(a.psi);
-  const C rot = mk<Real>(static_cast<Real>(a.rot_re), static_cast<Real>(a.rot_im));
-  const C pc = mk<Real>(static_cast<Real>(a.psi_coef_re), static_cast<Real>(a.psi_coef_im));
-  const uint32_t tmask = (1u << a.tile_bits) - 1u;
-  unsigned bid = blockIdx.x;
-  if (bid >= nitems) return;
-  const uint32_t item = xcd_tile(bid, nitems);
-  TileMap tm = make_tile_map(item & tmask, NB, a.c, a.p);
-  size_t voff = size_t(item >> a.tile_bits) * a.vstride;
-  C pf[NPT];
-#pragma unroll
-  for (int i = 0; i < NPT; ++i) pf[i] = xin[voff + tm.g(tid + i * T)];
-  for (;;) {
-#pragma unroll
-    for (int i = 0; i < NPT; ++i) lds[bw_phys(tid + i * T)] = pf[i];
-    const unsigned nbid = bid + gridDim.x;
-    const bool more = nbid < nitems;
-    TileMap tn = tm;
-    size_t vn = voff;
-    if (more) {
-      const uint32_t nitem = xcd_tile(nbid, nitems);
-      tn = make_tile_map(nitem & tmask, NB, a.c, a.p);
-      vn = size_t(nitem >> a.tile_bits) * a.vstride;
-#pragma unroll
-      for (int i = 0; i < NPT; ++i) pf[i] = xin[vn + tn.g(tid + i * T)];
-    }
-    __syncthreads();
-    for (int wi = 0; wi < a.nwin; ++wi) {
-      const WinU w = load_win(wins + wi);
-      const uint32_t below = (1u << w.b) - 1u;
-#pragma unroll 1
-      for (int gi = 0; gi < GPT; ++gi) {
-        const uint32_t g = uint32_t(tid + gi * T);
-        const int base = static_cast<int>((g & below) | ((g >> w.b) << (w.b + WB)));
-        C v[1 << WB];
-#pragma unroll
-        for (int m = 0; m < (1 << WB); ++m) v[m] = lds[bw_phys(base + (m << w.b))];
-        window_gates<Real, WB>(v, w, gates, mats);
-#pragma unroll
-        for (int m = 0; m < (1 << WB); ++m) lds[bw_phys(base + (m << w.b))] = v[m];
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < NPT; ++i) {
-      const int j = tid + i * T;
-      C x = lds[bw_phys(j)];
-      if (a.flags & BW_ROT) x = cmul(x, rot);
-      if constexpr (PSI) {
-        const C p = psi[voff + tm.g(j)];
-        x = (a.flags & BW_PSI_COEF) ? cfma(p, pc, x) : cadd(x, p);
-      }
-      xout[voff + tm.g(j)] = x;
-    }
-    if (!more) break;
-    __syncthreads();
-    bid = nbid;
-    tm = tn;
-    voff = vn;
-  }
-}
-
 size_t bw_lds_bytes(int n, size_t elem) { return size_t((1 << n) + (1 << (n - 4 > 0 ? n - 4 : 0)) + 1) * elem; }
 
-// Resident workgroups of a pipelined pass (CUs x workgroups per CU, a
-// multiple of 8), computed once per kernel.
-template <typename Real, int WB, int TB, int NB, bool PSI>
-hipError_t pipe_slots(int* slots) {
-  static int wgs_per_pass = 0;
-  if (wgs_per_pass == 0) {
-    const size_t shmem = bw_lds_bytes(NB, sizeof(cpx<Real>));
-    auto kern = bw_pipe_kernel<Real, WB, TB, NB, PSI>;
-    if (shmem > 65536) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem));
-      if (e != hipSuccess) return e;
-    }
-    int dev = 0, cus = 0, per_cu = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), 1 << TB, shmem);
-    if (e != hipSuccess) return e;
-    wgs_per_pass = std::max(8, (cus * std::max(1, per_cu)) & ~7);
-  }
-  *slots = wgs_per_pass;
-  return hipSuccess;
-}
-
-template <typename Real, int WB, int TB, int NB, bool PSI>
-hipError_t launch_bw_pipe(const BwPassArgs& a, unsigned nitems, hipStream_t s) {
-  int slots = 0;
-  hipError_t e = pipe_slots<Real, WB, TB, NB, PSI>(&slots);
-  if (e != hipSuccess) return e;
-  const size_t shmem = bw_lds_bytes(NB, sizeof(cpx<Real>));
-  const unsigned grid = std::min<unsigned>(nitems, static_cast<unsigned>(slots));
-  hipLaunchKernelGGL((bw_pipe_kernel<Real, WB, TB, NB, PSI>), dim3(grid), dim3(1 << TB), shmem, s, a, nitems,
-                     static_cast<const cpx<Real>*>(a.mats), a.wins, a.gates, static_cast<cpx<Real>*>(a.xout));
-  return hipGetLastError();
-}
-
-template <int WB, int TB>
+template <typename Real, int WB, int TB>
 hipError_t launch_bw_split(const BwPassArgs& a, unsigned nitems, hipStream_t s) {
-  const size_t shmem = bw_lds_bytes(a.n, sizeof(double));
-  auto kern = bw_pass_split_kernel<WB, TB>;
-  if (shmem > 65536) {
+  const size_t shmem = bw_lds_bytes(a.n, sizeof(Real));
+  auto kern = bw_pass_split_kernel<Real, WB, TB>;
+  static size_t attr_bytes = 65536;  // dynamic LDS admitted so far
+  if (shmem > attr_bytes) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem));
     if (e != hipSuccess) return e;
+    attr_bytes = shmem;
   }
-  hipLaunchKernelGGL(kern, dim3(nitems), dim3(1 << TB), shmem, s, a, static_cast<const cpx<double>*>(a.mats), a.wins,
+  hipLaunchKernelGGL(kern, dim3(nitems), dim3(1 << TB), shmem, s, a, static_cast<const cpx<Real>*>(a.mats), a.wins,
                      a.gates);
   return hipGetLastError();
 }
@@ -443,16 +330,13 @@ hipError_t launch_bw_t(const BwPassArgs& a, unsigned nitems, hipStream_t s) {
 // tiles, and for complex64 2^12), whose extra threads still share the tile's
 // loads and stores.
 hipError_t bw_launch_pass(const BwPassArgs& a, bool c64_dt, int wb, unsigned nitems, hipStream_t s) {
-  // complex64 2^13 / 2^14 tiles: the pipelined persistent form when every
-  // workgroup gets several tiles.  (The same form for complex128 2^11 / 2^12
-  // tiles lost to one-tile workgroups once the windows took up to eight
-  // gates: L = 20, 4 vectors, 32.5 against 31.1 us per U and vector.)
-  const bool ps = (a.flags & BW_ADD_PSI) != 0;
-  if (c64_dt && wb == 4 && nitems >= 1024 && nitems % 8 == 0 && (a.n == 13 || a.n == 14)) {
-    if (a.n == 13)
-      return ps ? launch_bw_pipe<float, 4, 9, 13, true>(a, nitems, s) : launch_bw_pipe<float, 4, 9, 13, false>(a, nitems, s);
-    return ps ? launch_bw_pipe<float, 4, 9, 14, true>(a, nitems, s) : launch_bw_pipe<float, 4, 9, 14, false>(a, nitems, s);
-  }
+  // complex64 2^13- and 2^14-amplitude tiles: one window group per thread
+  // (512 and 1024 threads), planes through 34 and 68 KiB of LDS.  Against
+  // a persistent kernel that kept the whole tile in LDS (136 KiB for 2^14:
+  // one workgroup per CU) and prefetched the next tile into registers, the
+  // L = 24 Horner step went from 359 to 272 us.
+  if (c64_dt && wb == 4 && a.n == 13) return launch_bw_split<float, 4, 9>(a, nitems, s);
+  if (c64_dt && wb == 4 && a.n == 14) return launch_bw_split<float, 4, 10>(a, nitems, s);
   const int tb_max = (a.n >= 13 || (c64_dt && a.n >= 12)) ? 9 : 8;
   int tb = std::max(6, std::min(tb_max, a.n - wb));
   while (tb < tb_max && (static_cast<uint64_t>(nitems) << (tb - 6)) < 1024u) ++tb;
@@ -472,8 +356,8 @@ hipError_t bw_launch_pass(const BwPassArgs& a, bool c64_dt, int wb, unsigned nit
     // smaller LDS gains, since registers already limit those to one
     // workgroup per CU: 651 -> 664 us per step at L = 24)
     if (wb == 4 && tb == a.n - 4 && tb <= 8) {
-      if (tb == 8) return launch_bw_split<4, 8>(a, nitems, s);
-      if (tb == 7) return launch_bw_split<4, 7>(a, nitems, s);
+      if (tb == 8) return launch_bw_split<double, 4, 8>(a, nitems, s);
+      if (tb == 7) return launch_bw_split<double, 4, 7>(a, nitems, s);
     }
     if (wb == 4) {
       if (tb == 9) return launch_bw_t<double, 4, 9>(a, nitems, s);

@@ -91,14 +91,15 @@ def summarise(fetch_csv, write_csv, copy_bytes, family="ki"):
     fam = FAMILIES[family]
 
     def real_of(name):
-        # the precision of a pass kernel from its template arguments (the
-        # plane-split brickwork pass is complex128 only)
+        # the precision of a pass kernel from its first template argument
+        # (traces of the plane-split brickwork pass from before it took one,
+        # when it was complex128 only, have an integer there)
         for t in fam["kernels"]:
-            if "split" in t and f"{t}<" in name:
-                return "double"
             for r in ("float", "double"):
                 if f"{t}<{r}" in name:
                     return r
+            if "split" in t and f"{t}<" in name:
+                return "double"
         return None
 
     passes = {}
