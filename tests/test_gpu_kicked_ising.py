@@ -7,7 +7,7 @@ import math
 import numpy as np
 import pytest
 
-from gpu_util import ki_op, rel, require_gpu, say, to_dev, to_np
+from gpu_util import ki_op, memo, rel, require_gpu, say, to_dev, to_np
 from oracle import filters, models
 from workloads import KickedIsingParams, kicked_ising, random_state
 
@@ -85,6 +85,45 @@ def test_apply_U_large_special_cases(dt, L, g):
             pref = 1.0 if gg == 0.0 else (-1j) ** L
             expect = pref * cmath.exp(-1j * E) * psi[s]
             assert abs(out[sp] - expect) < bound
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_apply_filter_L25_special_cases(dt):
+    # the filter on the three-tile-group schedule of L = 25, sampled against
+    # closed forms (Eq. (geo) with U from the two special points):
+    #   g = 0:    U psi(s) = e^{-iE(s)} psi(s), so the filter is the geometric
+    #             sum of z e^{-iE(s)}, z = e^{-i phi}, times psi(s);
+    #   g = pi/2: U psi(t) = c e^{-iE(t)} psi(t'), c = (-i)^L, t' the
+    #             complement of t, so with k = 2 the filter at t is
+    #             psi(t) + z c e^{-iE(t)} psi(t') + z^2 c^2 e^{-iE(t)} e^{-iE(t')} psi(t)
+    L, k, phi = 25, 2, 0.7
+    d = 2 ** L
+
+    def draw():
+        rng = np.random.default_rng(2500)
+        v = (rng.standard_normal(d) + 1j * rng.standard_normal(d)) / math.sqrt(2 * d)
+        return v, rng.integers(0, d, size=200)
+    psi, idx = memo(("psi", L, 2500), draw)
+    z = cmath.exp(-1j * phi)
+    c = (-1j) ** L
+    for gg in (0.0, math.pi / 2):
+        say(f"apply_filter L=25 special case g={gg:.4f} {dt}")
+        p = kicked_ising(L, 320, g=gg)
+        E = memo(("ki-E", L, 320, gg), lambda: models.ki_energies(L, p.J, p.h, p.periodic))
+        with ki_op(p) as op:
+            out = to_np(op.apply_filter(to_dev(psi, _dt(dt)), k, phi))
+        scale = np.max(np.abs(out))
+        for t in idx:
+            tc = (d - 1) ^ int(t)
+            if gg == 0.0:
+                w = z * cmath.exp(-1j * E[t])
+                expect = (1 + w + w * w) * psi[t]
+            else:
+                expect = (psi[t] + z * c * cmath.exp(-1j * E[t]) * psi[tc]
+                          + z * z * c * c * cmath.exp(-1j * (E[t] + E[tc])) * psi[t])
+            tol = 1e-12 * (k + 1) if dt == "c128" else 2e-7 * (k + 1) + 2e-6
+            assert abs(out[t] - expect) < tol * scale, (gg, int(t), abs(out[t] - expect) / scale)
+        del out
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
