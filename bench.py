@@ -435,7 +435,7 @@ def brickwork_filter(args):
         # FP32 units without packed instructions (78.6 TFLOP/s / 8 TB/s = 9.8)
         "roofline": {"bound": "alu", "achieved": c64["TFLOPs"], "peak": 78.6, "unit": "TFLOP/s",
                      "frac": c64["TFLOPs"] / 78.6, "traffic": None,
-                     "kernel": "bw_pipe_kernel / bw_pass_kernel (right block + left block per Horner step)",
+                     "kernel": "bw_pass_split_kernel (complex64; bw_pass_kernel for complex128), right block + left block per Horner step",
                      "hbm_GBs": c64["alg_GBs"], "hbm_frac": c64["alg_GBs"] / 8000.0},
         "c128": out["c128"],
     }

@@ -36,6 +36,7 @@ FAMILIES = {
     "ki": {"kernels": ("ki_pass_kernel", "ki_pass3_kernel"),
            "sources": ["csrc/ki_kernels_impl.h", "csrc/tile_engine.h", "csrc/ki_kernels.h"],
            "launches_per_step": 1},
+    # (bw_pipe_kernel: the persistent brickwork pass of earlier traces)
     "bw": {"kernels": ("bw_pass_kernel", "bw_pipe_kernel", "bw_pass_split_kernel"),
            "sources": ["csrc/bw_kernels.hip", "csrc/tile_engine.h", "csrc/bw_kernels.h"],
            "launches_per_step": 2},
